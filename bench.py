@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark: He walker-steps/s on one MI355X, mixed (FP32 step, FP64 ln w and
+reductions) against all-FP64, and the time to a 1e-5 Ha statistical error.
+
+A step is one pass of the whole path over one seed of the workload: start
+ensemble (Metropolis), propagation over all n_steps with the log-domain space
+average at every sampling time, sample rows back to the host, energy
+estimators.  value = n_walkers * n_steps / (wall time of one step).
+
+Default workload: the 2^1P (P_z) trial, 2^24 walkers, dt = 0.0005, T = 6
+(12000 steps), sampled every 100 steps.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="he_2P_pz_16m")
+    ap.add_argument("--precision", default=None, help="override the workload's precision")
+    ap.add_argument("--noise", default=None)
+    ap.add_argument("--contract", type=int, default=None)
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 steps for the speedup (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-walkers", type=int, default=16384)
+    return ap.parse_args()
+
+
+def run_leg(cfg, n_steps_timed, n_warmup, seeds):
+    """Time full steps; returns per-step wall times, kernel times, energies, block errors."""
+    import torch
+    from paper_1703_08977_amd import Ensemble, he_fk_energy
+    from paper_1703_08977_amd.stats import jackknife
+
+    ens = Ensemble(cfg)
+    ns = cfg["n_steps"] // cfg["sample_every"] + 1
+    samples = torch.empty((ns, 8), dtype=torch.float64, device="cuda")
+    ens.workspace(cfg["n_steps"], cfg["sample_every"])
+    dts = cfg["dt"] * cfg["sample_every"]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def one(seed):
+        ens.p.seed = seed
+        ens.init()
+        ev0.record()
+        ens.propagate(0, cfg["n_steps"], cfg["sample_every"], samples=samples)
+        ev1.record()
+        host = samples.cpu().numpy()  # synchronises the stream
+        e_win = he_fk_energy(host, dts, cfg["e_ref"], "window")[0][0]
+        return host, e_win
+
+    for i in range(n_warmup):
+        one(10_000 + i)
+        print("# warmup %d done (%s)" % (i, cfg["precision"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    walls, kern, energies, errs = [], [], [], []
+    for i in range(n_steps_timed):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host, e_win = one(seeds[i])
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kern.append(ev0.elapsed_time(ev1) / 1e3)
+        rows = ens.block_rows(cfg["n_steps"], cfg["sample_every"]).cpu().numpy()
+        e_jk, s_jk = jackknife(rows, dts, cfg["e_ref"], "window")
+        energies.append(e_win)
+        errs.append(s_jk)
+        print("# step %d (%s): wall %.3f s, propagate %.3f s, E_win %.7f +- %.7f" %
+              (i, cfg["precision"], walls[-1], kern[-1], e_win, s_jk), file=sys.stderr, flush=True)
+    del ens
+    torch.cuda.empty_cache()
+    return dict(walls=walls, kern=kern, energies=energies, errs=errs)
+
+
+def cpu_baseline(cfg, n_walkers):
+    """The oracle (FP64, OpenMP) on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    ids = np.arange(n_walkers)
+    c = dict(cfg, precision="fp64")
+    t0 = time.perf_counter()
+    x, _ = oracle.init(c, ids)
+    t1 = time.perf_counter()
+    oracle.propagate(c, ids, x, np.zeros(n_walkers), 0, cfg["n_steps"], cfg["sample_every"], record=False)
+    t2 = time.perf_counter()
+    ws = n_walkers * cfg["n_steps"]
+    return {"value": ws / (t2 - t0), "unit": "walker-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "walker ids 0..%d of the workload, all %d steps, start ensemble included "
+                      "(start %.2f s, propagation %.2f s, propagation-only %.4g walker-steps/s)" %
+                      (n_walkers - 1, cfg["n_steps"], t1 - t0, t2 - t1, ws / (t2 - t1))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "
+              "reduction, and this build measures one MI355X (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1703_08977_amd import workloads as W
+    from paper_1703_08977_amd.roofline import PEAK_SLOTS_PER_S, fp32_flops_per_walker_step, slots_per_walker_step
+
+    over = {}
+    if args.precision:
+        over["precision"] = args.precision
+    if args.noise:
+        over["noise"] = args.noise
+    if args.contract:
+        over["contract"] = args.contract
+    cfg = W.get(args.workload, **over)
+    n, K = cfg["n_walkers"], cfg["n_steps"]
+    seeds = list(range(args.steps))
+
+    main_leg = run_leg(cfg, args.steps, args.warmup, seeds)
+    wall = sum(main_leg["walls"]) / len(main_leg["walls"])
+    kern = sum(main_leg["kern"]) / len(main_leg["kern"])
+    value = n * K / wall
+
+    slots = slots_per_walker_step(cfg)
+    achieved = slots * n * K / kern / 1e12
+    peak = PEAK_SLOTS_PER_S / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "propagate_kernel", "slots_per_walker_step": slots,
+            "kernel_ms": kern * 1e3}
+    fl = fp32_flops_per_walker_step(cfg)
+    if fl:
+        roof["fp32_tflops"] = fl * n * K / kern / 1e12
+        roof["fp32_flop_frac_of_157.3"] = roof["fp32_tflops"] / 157.3
+
+    out = {
+        "metric": "He walker-steps/s/GPU; mixed FP32 vs FP64 time-to-1e-5 Ha energy error",
+        "value": value, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if cfg["precision"] == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "trial": cfg["trial"], "sym": cfg.get("sym", 1),
+                   "n_walkers": n, "n_steps": K, "dt": cfg["dt"], "T": K * cfg["dt"],
+                   "sample_every": cfg["sample_every"], "precision": cfg["precision"],
+                   "noise": cfg["noise"], "contract": cfg["contract"], "quad": cfg["quad"],
+                   "n_metropolis": cfg["n_metropolis"], "seeds": seeds},
+        "propagate_walker_steps_per_s": n * K / kern,
+        "roofline": roof,
+        "energy": {"E_window": main_leg["energies"], "jackknife_se": main_leg["errs"]},
+    }
+
+    if args.fp64_steps > 0 and cfg["precision"] == "mixed":
+        c64 = dict(cfg, precision="fp64")
+        leg = run_leg(c64, args.fp64_steps, 0, seeds[:args.fp64_steps])
+        w64 = sum(leg["walls"]) / len(leg["walls"])
+        k64 = sum(leg["kern"]) / len(leg["kern"])
+        out["fp64"] = {"value": n * K / w64, "ms_per_step": w64 * 1e3, "propagate_walker_steps_per_s": n * K / k64,
+                       "E_window": leg["energies"], "jackknife_se": leg["errs"],
+                       "slots_per_walker_step": slots_per_walker_step(c64)}
+        out["speedup_mixed_vs_fp64"] = w64 / wall
+        # paired mixed - FP64 difference on identical seeds, and the time to a 1e-5 Ha standard error
+        m = len(leg["energies"])
+        d = [main_leg["energies"][i] - leg["energies"][i] for i in range(m)]
+        bias = sum(d) / m
+        eps = 1e-5
+        s_mix = sum(main_leg["errs"]) / len(main_leg["errs"])
+        s_64 = sum(leg["errs"]) / m
+        t_mix = wall * s_mix ** 2 / (eps ** 2 - bias ** 2) if abs(bias) < eps else math.inf
+        t_64 = w64 * s_64 ** 2 / eps ** 2
+        out["time_to_1e-5_Ha"] = {"mixed_s": t_mix, "fp64_s": t_64,
+                                  "speedup": (t_64 / t_mix) if math.isfinite(t_mix) else 0.0,
+                                  "paired_bias_mixed_minus_fp64": bias, "sigma_mixed": s_mix, "sigma_fp64": s_64,
+                                  "note": "statistical error only; the time-step bias is common to both precisions"}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_walkers)
+        print("# cpu baseline done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    torch.cuda.synchronize()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * he_fk.h -- C ABI of libhefk: importance-sampled (generalized) Feynman-Kac
+ * propagation of two-electron (He) walkers on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Datta, Rejcek, Fry, "The He atom revisited", arXiv:1703.08977):
+ *   The lowest eigenvalue of H = -Lap/2 + V on R^6, V = -Z/r1 - Z/r2 + 1/r12,
+ *   follows from eq. (4):
+ *     lambda1 = lambda0 - lim_t (1/t) ln E[ exp(-int_0^t V_P(Y(s)) ds) ],
+ *   with V_P = E_L - lambda0, E_L = -(1/2) Lap(psi_T)/psi_T + V the local
+ *   energy of the trial function psi_T (the paper's V0 lacks the factor 1/2
+ *   on Lap(phi)/phi; with it psi_T^2 is the stationary law of Y), and Y the
+ *   drifted diffusion dY = grad(psi_T)/psi_T dt + dX that follows eq. (4).
+ *   The expectation is a space average over independent replications
+ *   (walkers), kept in the log domain: L(t) = ln( (1/N) sum_i w_i(t) ),
+ *   ln w_i = -sum_k V_P dt along walker i's discretised path.  Walkers of
+ *   excited-state trials are absorbed when they cross the node of psi_T.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are caller-owned device memory; the library never
+ *     allocates device memory.  Host pointers are named so in each comment.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     null stream); outputs are valid after that stream synchronises.
+ *   - Return 0 on success or a negative HE_FK_E* code; nothing is enqueued
+ *     when an argument check fails.  No exception crosses the ABI.  The
+ *     library holds no mutable global state: calls on distinct buffers may
+ *     run concurrently from different threads.
+ */
+#ifndef HE_FK_H
+#define HE_FK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define HE_FK_OK 0
+#define HE_FK_EINVAL (-1)     /* an argument is out of range or inconsistent            */
+#define HE_FK_EDEVICE (-2)    /* a HIP call failed (no device, launch error, ...)         */
+#define HE_FK_ENONFINITE (-3) /* a sample row counts walkers with non-finite ln w / E_L   */
+#define HE_FK_EALLDEAD (-4)   /* a sample row has no live walker (all absorbed)          */
+#define HE_FK_ESCRATCH (-5)   /* workspace / scratch smaller than the size query returns */
+
+/* ---- trial functions psi_T (theta = {t0, t1, t2, t3}) ---- */
+/* exp(-t0 (r1 + r2)).  With Z = 2, ee = 0, t0 = 2 it is exact (E_L = -4);
+   with Z = 1, ee = 0, t0 = 1 it is two hydrogen atoms (E_L = -1). */
+#define HE_FK_TRIAL_EXPO 0
+/* exp(-t0 (r1 + r2)) exp(t2 r12 / (1 + t1 r12))  (Pade-Jastrow, ground state) */
+#define HE_FK_TRIAL_PADE 1
+/* [exp(-t0 r1 - t3 r2) - exp(-t0 r2 - t3 r1)] exp(t2 r12 / (1 + t1 r12));
+   node r1 = r2, the exact node of the 2^3S state (trial functions 3-6 of the
+   paper share it) */
+#define HE_FK_TRIAL_TRIPLET 2
+/* [z2 exp(-t0 r1 - t3 r2) + sym z1 exp(-t0 r2 - t3 r1)] exp(t2 r12 / (1 + t1 r12));
+   odd under z -> -z for both electrons (a P_z state, cf. trial function 7) */
+#define HE_FK_TRIAL_PZ 3
+
+#define HE_FK_FP64 0  /* coordinates, drift, E_L, ln w all binary64                       */
+#define HE_FK_MIXED 1 /* coordinates, drift, E_L binary32; ln w, reductions binary64     */
+
+#define HE_FK_NOISE_GAUSS 0 /* Euler-Maruyama: sqrt(dt) xi, xi ~ N(0, I_6) by Box-Muller   */
+#define HE_FK_NOISE_PM1 1   /* the paper's walk: sqrt(dt) eps, eps_j = +-1 w.p. 1/2 each   */
+
+#define HE_FK_QUAD_TRAPEZOID 0 /* ln w -= dt/2 [(E_L(Y_k) - e_ref) + (E_L(Y_k+1) - e_ref)]  */
+#define HE_FK_QUAD_RIGHT 1     /* ln w -= dt (E_L(Y_k+1) - e_ref): the paper's Riemann sum    */
+
+/*
+ * Random stream contract (Philox4x32-10, Salmon et al. SC'11).  The counter of
+ * block b is (b, phase, lo32(g), hi32(g)) for global walker id
+ * g = walker_offset + i, the key is (lo32(seed), hi32(seed)).  Phase 0: start
+ * draw; 1: Metropolis; 2: Gaussian propagation; 3: +-1 propagation.  The
+ * propagation draw of global step k depends on k only, so calls are
+ * resumable.
+ *   contract 1: Gaussian vector k uses blocks 2k, 2k+1; uniforms (w + 1/2) 2^-32
+ *               from words (a0,a1), (a2,a3), (b0,b1) (binary32 runs use the top
+ *               23 bits: ((w >> 9) + 1/2) 2^-23).
+ *   contract 2: Gaussian vector k uses block k; six 21-bit fields
+ *               f_j = w_j & (2^21 - 1) (j < 4), f_4 = (w0 >> 21) | ((w1 >> 21) & 1023) << 11,
+ *               f_5 = (w2 >> 21) | ((w3 >> 21) & 1023) << 11; uniforms (f + 1/2) 2^-21,
+ *               identical in both precisions.
+ *   +-1 walk:   step k reads block k / 20, word (k mod 20) / 5, bits 6 (k mod 5) + j.
+ * The start ensemble always uses contract 1 in binary64 (both precisions start
+ * from the same walkers).
+ */
+
+typedef struct {
+    int32_t trial;        /* HE_FK_TRIAL_* */
+    int32_t sym;          /* +1 or -1 (HE_FK_TRIAL_PZ only) */
+    int32_t ee;           /* 1: V holds +1/r12; 0: independent electrons */
+    int32_t noise;        /* HE_FK_NOISE_* */
+    int32_t quad;         /* HE_FK_QUAD_* */
+    int32_t contract;     /* 1 or 2 (Gaussian noise only) */
+    int32_t precision;    /* HE_FK_FP64 or HE_FK_MIXED */
+    int32_t n_metropolis; /* Metropolis steps of the start ensemble (>= 0) */
+    double Z;             /* nuclear charge (> 0) */
+    double theta[4];      /* trial parameters, see HE_FK_TRIAL_* */
+    double dt;            /* time step (> 0) */
+    double e_ref;         /* trial energy lambda0 of eq. (4); shifts ln w, cancels in E */
+    double metropolis_sigma; /* Metropolis proposal width (> 0) */
+    double init_sigma;    /* width of the Gaussian the Metropolis chain starts from (> 0) */
+    uint64_t seed;        /* Philox key */
+    uint64_t walker_offset; /* global id of walker 0 of this call (shards of one ensemble) */
+    int64_t n_walkers;    /* N >= 1 */
+} he_fk_params;
+
+/* Walker state, structure of arrays in device memory:
+ *   x   [6][N]: x1 y1 z1 x2 y2 z2 rows, binary64 (FP64) or binary32 (MIXED);
+ *   lnw [N]   : ln w, binary64.  -inf: absorbed at the node.  NaN: the walker
+ *               met a non-finite local energy (kept NaN from then on);
+ *   el  [N]   : E_L at the current position, binary64 or binary32 (output). */
+typedef struct {
+    void* x;
+    double* lnw;
+    void* el;
+} he_fk_walkers;
+
+/*
+ * he_fk_init: the start ensemble Y0 ~ psi_T^2 (the start point of eq. (4) is
+ * left open by the paper; a |psi_T|^2 start makes L(0) = 0 and E_mixed(0)
+ * the variational energy).  Per walker: Y = init_sigma * xi(phase 0,
+ * vector 0); then n_metropolis steps Y' = Y + metropolis_sigma * xi(phase 1,
+ * vector m), accepted iff ln u < 2 (ln|psi(Y')| - ln|psi(Y)|), u the uniform
+ * of word 2 of block 2m+1.  Writes x, el = E_L(Y0), lnw = 0.
+ * Errors: EINVAL (bad params / NULL pointers), EDEVICE.
+ */
+int he_fk_init(const he_fk_params* p, const he_fk_walkers* w, void* stream);
+
+/* Bytes of device workspace he_fk_propagate needs (per-block partial sample
+   rows); 0 when the arguments are invalid or no device is present. */
+size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, int32_t sample_every);
+
+/*
+ * he_fk_propagate: advance every walker over global steps [step0, step0 + n_steps)
+ * (drifted diffusion after eq. (4), discretised as in the paper's random-walk
+ * construction; absorption at the node for the TRIPLET and PZ trials):
+ *   Y' = Y + dt b(Y) + sqrt(dt) xi_k,  b = grad ln|psi_T|;
+ *   absorbed (lnw = -inf, frozen) iff sign psi_T(Y') != sign psi_T(Y) or psi_T(Y') = 0;
+ *   else ln w updated by the quadrature rule and Y = Y'.
+ * samples [n_steps / sample_every + 1][8] (device, binary64): row s is the
+ * space average at step step0 + s * sample_every (row 0 = the state on entry):
+ *   (m, S0, S1, S2, n_alive, n_nonfinite, n_total, 0) with m = max ln w over
+ *   live walkers, S0 = sum e^(lnw - m), S1 = sum e^(lnw - m) E_L,
+ *   S2 = sum e^(2 (lnw - m)); so L = m + ln S0 - ln n_total.
+ * The reduction tree is fixed, so repeated calls are bitwise identical.
+ * ckpt (device, binary64, may be NULL; FP64 precision only):
+ *   [n_steps / ckpt_every + 1][7][N], rows x1..z2, lnw at steps step0 + c * ckpt_every.
+ * workspace: at least he_fk_propagate_workspace_bytes(p, n_steps, sample_every) bytes.
+ *   On return its first bytes hold the per-block partial rows [G][n_samples][8]
+ *   (G = that size / (64 n_samples)), each over a fixed subset of walkers, whose
+ *   merge is `samples` (usable for block error bars).
+ * Constraints: n_steps >= 0, sample_every >= 1, n_steps % sample_every == 0,
+ * ckpt_every >= 1 and n_steps % ckpt_every == 0 when ckpt != NULL, step0 >= 0,
+ * step0 + n_steps < 2^31.
+ * Errors: EINVAL, ESCRATCH, EDEVICE.
+ */
+int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,
+                    int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- energy estimators (host only, pure) ---- */
+#define HE_FK_E_FD 0     /* E_out[n_samples-1]: e_ref - (L_j - L_{j-1}) / dt_sample            */
+#define HE_FK_E_WINDOW 1 /* E_out[1]: e_ref - least-squares slope of L(t) over t in [T/2, T]   */
+#define HE_FK_E_FIT 2    /* E_out[2]: {e_ref - b, a} of the least-squares fit L/t = b + a/t,
+                            t > 0, weights fit_w[n_samples] (NULL: equal); the paper's
+                            "ls fit" with lambda1 = lambda0 - b (Tables 1-5)                 */
+#define HE_FK_E_MIXED 3  /* E_out[n_samples]: S1 / S0, the weighted mean local energy       */
+
+/*
+ * he_fk_energy: estimators from sample rows (HOST memory, as written by
+ * he_fk_propagate and copied back).  Row j is at time t_j = j * dt_sample.
+ * aux_out (host, may be NULL): [n_samples][2] = (L_j, S0_j^2 / S2_j) - the log
+ * space average and the effective sample size.
+ * Errors: EINVAL, ENONFINITE (a row counts non-finite walkers),
+ * EALLDEAD (a row has no live walker).  aux_out is filled before these two
+ * are reported.
+ */
+int he_fk_energy(const double* samples, int64_t n_samples, double dt_sample, double e_ref, int32_t method,
+                 const double* fit_w, double* E_out, double* aux_out);
+
+/* ---- pathwise gradient (adjoint) ---- */
+#define HE_FK_GRAD_SCORE 1 /* add the derivative of the |psi_T|^2 start law (score term) */
+
+/* Bytes of device scratch he_fk_grad needs; 0 on invalid arguments. */
+size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_steps, int32_t sample_every,
+                                int32_t ckpt_every);
+
+/*
+ * he_fk_grad: d/d(theta0, theta1) of J = sum_s gL[s] L_s (L_s the log space
+ * average of sample row s of a he_fk_propagate call from step 0), for the
+ * nodeless trials (EXPO, PADE) in FP64, at fixed start positions and fixed
+ * noise (pathwise / fixed-noise derivative of the discrete map), by a reverse
+ * sweep over checkpoint segments with the noise regenerated from Philox.
+ *   y0      : walker state at step 0 (x read; lnw, el ignored);
+ *   ckpt    : device, the checkpoints of that propagate call;
+ *   samples : device, its sample rows (m and S0 give the walker weights);
+ *   gL      : HOST, [n_steps / sample_every + 1];
+ *   flags   : 0 or HE_FK_GRAD_SCORE;
+ *   dtheta  : device, [2] binary64 output.
+ * Constraints: as he_fk_propagate with ckpt != NULL; ckpt_every % sample_every == 0
+ * or sample_every % ckpt_every == 0.
+ * Errors: EINVAL (also for node trials or MIXED precision), ESCRATCH, EDEVICE.
+ */
+int he_fk_grad(const he_fk_params* p, const he_fk_walkers* y0, const double* ckpt, const double* samples,
+               const double* gL, int64_t n_steps, int32_t sample_every, int32_t ckpt_every, int32_t flags,
+               void* scratch, size_t scratch_bytes, double* dtheta, void* stream);
+
+/* Static description of an error code. */
+const char* he_fk_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HE_FK_H */

@@ -1,0 +1,503 @@
+// hefk_device.hpp -- per-walker arithmetic of the generalized Feynman-Kac
+// propagation: Philox4x32-10 stream, noise maps, trial functions (ln|psi|,
+// sign, drift, local energy), one walker step.  Host+device code: the HIP
+// kernels run it on gfx950, and a host build of the same code serves the
+// CPU checks of the kernels' arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#define HD __host__ __device__ __forceinline__
+
+namespace hefk {
+
+enum : int { TRIAL_EXPO = 0, TRIAL_PADE = 1, TRIAL_TRIPLET = 2, TRIAL_PZ = 3 };
+// noise kinds of the kernels: Gaussian under contract 1, Gaussian under contract 2, +-1 walk
+enum : int { NOISE_G1 = 0, NOISE_G2 = 1, NOISE_PM1 = 2 };
+enum : uint32_t { PHASE_INIT = 0, PHASE_METROPOLIS = 1, PHASE_GAUSS = 2, PHASE_PM1 = 3 };
+
+template <int TRIAL>
+struct has_node {
+    static constexpr bool value = (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_PZ);
+};
+
+// ---------------------------------------------------------------------------
+// Elementary functions.  binary64: the correctly rounded sqrt and division and
+// the device math library for the transcendentals.  binary32: the hardware
+// approximations (v_sqrt_f32, v_rcp_f32, v_exp_f32, v_log_f32 and
+// v_sin_f32 / v_cos_f32, which take their argument in revolutions).
+// ---------------------------------------------------------------------------
+namespace m {
+
+HD double sqrt_(double x) { return ::sqrt(x); }
+HD double rcp_(double x) { return 1.0 / x; }
+HD double exp_(double x) { return ::exp(x); }
+HD double expm1_(double x) { return ::expm1(x); }
+HD double log_(double x) { return ::log(x); }
+// sin(2 pi u), cos(2 pi u) for u in (0, 1)
+HD void sincos2pi(double u, double* s, double* c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    ::sincospi(2.0 * u, s, c);
+#else
+    const double two_pi = 6.283185307179586476925286766559;
+    *s = ::sin(two_pi * u);
+    *c = ::cos(two_pi * u);
+#endif
+}
+
+HD float sqrt_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return ::sqrtf(x);
+#endif
+}
+HD float rcp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+HD float exp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+#else
+    return ::expf(x);
+#endif
+}
+HD float expm1_(float x) { return ::expm1f(x); }
+HD float log_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+#else
+    return ::logf(x);
+#endif
+}
+HD void sincos2pi(float u, float* s, float* c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+#else
+    *s = ::sinf(6.2831853071795865f * u);
+    *c = ::cosf(6.2831853071795865f * u);
+#endif
+}
+
+}  // namespace m
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit products with the round constants below, the key bumped by
+// the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct Words {
+    uint32_t w[4];
+};
+
+HD Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words o;
+    o.w[0] = c0;
+    o.w[1] = c1;
+    o.w[2] = c2;
+    o.w[3] = c3;
+    return o;
+}
+
+struct Stream {
+    uint32_t k0, k1;  // key: the seed
+    uint32_t g0, g1;  // counter words 2, 3: the global walker id
+    HD Words block(uint32_t phase, uint32_t b) const { return philox(b, phase, g0, g1, k0, k1); }
+};
+
+// uniform (0,1) from a 32-bit word: binary64 (w + 1/2) 2^-32; binary32 from the top 23 bits
+HD double unit32(uint32_t w, double) { return ((double)w + 0.5) * 0x1p-32; }
+HD float unit32(uint32_t w, float) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+// uniform (0,1) from a 21-bit field, exact in both precisions
+template <typename R>
+HD R unit21(uint32_t f)
+{
+    return ((R)f + (R)0.5) * (R)0x1p-21;
+}
+
+template <typename R>
+HD void box_muller(R u1, R u2, R* a, R* b)
+{
+    const R rad = m::sqrt_((R)-2.0 * m::log_(u1));
+    R s, c;
+    m::sincos2pi(u2, &s, &c);
+    *a = rad * c;
+    *b = rad * s;
+}
+
+// Gaussian 6-vector number v of a phase, contract 1 (blocks 2v, 2v+1); returns
+// the spare uniform of word 2 of the second block in *spare (binary64).
+template <typename R>
+HD void gauss6_c1(const Stream& st, uint32_t phase, uint32_t v, R xi[6], double* spare)
+{
+    const Words a = st.block(phase, 2u * v);
+    const Words b = st.block(phase, 2u * v + 1u);
+    box_muller<R>(unit32(a.w[0], R()), unit32(a.w[1], R()), &xi[0], &xi[1]);
+    box_muller<R>(unit32(a.w[2], R()), unit32(a.w[3], R()), &xi[2], &xi[3]);
+    box_muller<R>(unit32(b.w[0], R()), unit32(b.w[1], R()), &xi[4], &xi[5]);
+    if (spare) *spare = unit32(b.w[2], 0.0);
+}
+
+// contract 2: one block, six 21-bit fields
+template <typename R>
+HD void gauss6_c2(const Stream& st, uint32_t phase, uint32_t v, R xi[6])
+{
+    const Words a = st.block(phase, v);
+    const uint32_t m21 = 0x1FFFFFu;
+    const uint32_t f4 = (a.w[0] >> 21) | (((a.w[1] >> 21) & 0x3FFu) << 11);
+    const uint32_t f5 = (a.w[2] >> 21) | (((a.w[3] >> 21) & 0x3FFu) << 11);
+    box_muller<R>(unit21<R>(a.w[0] & m21), unit21<R>(a.w[1] & m21), &xi[0], &xi[1]);
+    box_muller<R>(unit21<R>(a.w[2] & m21), unit21<R>(a.w[3] & m21), &xi[2], &xi[3]);
+    box_muller<R>(unit21<R>(f4), unit21<R>(f5), &xi[4], &xi[5]);
+}
+
+// +-1 walk: step k uses bits 6 (k mod 5) + j of word (k mod 20) / 5 of block k / 20
+template <typename R>
+HD void pm1_from_word(uint32_t word, uint32_t k, R xi[6])
+{
+    const uint32_t sh = 6u * (k % 5u);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) xi[j] = ((word >> (sh + (uint32_t)j)) & 1u) ? (R)1 : (R)-1;
+}
+
+// The propagation noise of global step k for one walker.  The +-1 walk keeps
+// the Philox block it is reading (one block serves 20 steps).
+template <typename R, int NOISE>
+struct NoiseGen {
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, blk = 0xFFFFFFFFu;
+
+    HD void draw(const Stream& st, uint32_t k, R xi[6])
+    {
+        if (NOISE == NOISE_G1) {
+            gauss6_c1<R>(st, PHASE_GAUSS, k, xi, nullptr);
+        } else if (NOISE == NOISE_G2) {
+            gauss6_c2<R>(st, PHASE_GAUSS, k, xi);
+        } else {
+            const uint32_t b = k / 20u;
+            if (b != blk) {
+                const Words ww = st.block(PHASE_PM1, b);
+                w0 = ww.w[0];
+                w1 = ww.w[1];
+                w2 = ww.w[2];
+                w3 = ww.w[3];
+                blk = b;
+            }
+            const uint32_t wi = (k % 20u) / 5u;
+            const uint32_t word = wi == 0 ? w0 : (wi == 1 ? w1 : (wi == 2 ? w2 : w3));
+            pm1_from_word<R>(word, k, xi);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Trial functions.  psi = Phi exp(U), U = c r12 / (1 + beta r12).
+// Parameters: A = theta0 (orbital exponent), beta = theta1, c = theta2,
+// a = theta3 (second exponent, TRIPLET and PZ).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct TrialParams {
+    R A, beta, c, a, Z, ee, sym;
+};
+
+// Pieces of the geometry every trial uses.
+template <typename R>
+struct Geo {
+    R h1[3], h2[3], h12[3];  // unit vectors r1/|r1|, r2/|r2|, (r1-r2)/|r1-r2|
+    R r1, r2, r12, i1, i2, i12;
+};
+
+template <typename R>
+HD void geometry(const R y[6], Geo<R>& g)
+{
+    const R d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
+    g.r1 = m::sqrt_(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    g.r2 = m::sqrt_(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+    g.r12 = m::sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
+    g.i1 = m::rcp_(g.r1);
+    g.i2 = m::rcp_(g.r2);
+    g.i12 = m::rcp_(g.r12);
+    g.h1[0] = y[0] * g.i1;
+    g.h1[1] = y[1] * g.i1;
+    g.h1[2] = y[2] * g.i1;
+    g.h2[0] = y[3] * g.i2;
+    g.h2[1] = y[4] * g.i2;
+    g.h2[2] = y[5] * g.i2;
+    g.h12[0] = d0 * g.i12;
+    g.h12[1] = d1 * g.i12;
+    g.h12[2] = d2 * g.i12;
+}
+
+// Jastrow pieces: u' = c / s^2, u'' = -2 c beta / s^3, and
+// (ee - 2 u') / r12 written without the cancellation at r12 -> 0 when
+// ee = 2c (the cusp value): (ee - 2c)/r12 + 2c beta (2 + beta r12) / s^2,
+// from 1 - 1/s^2 = beta r12 (2 + beta r12) / s^2.
+template <typename R>
+struct Jas {
+    R up, upp, ee_term;
+};
+
+template <typename R>
+HD Jas<R> jastrow(const TrialParams<R>& p, const Geo<R>& g)
+{
+    Jas<R> j;
+    const R is = m::rcp_((R)1 + p.beta * g.r12);
+    const R is2 = is * is;
+    j.up = p.c * is2;
+    j.upp = (R)-2 * p.c * p.beta * is2 * is;
+    const R cusp = p.ee - (R)2 * p.c;
+    j.ee_term = (R)2 * p.c * p.beta * ((R)2 + p.beta * g.r12) * is2 + (cusp != (R)0 ? cusp * g.i12 : (R)0);
+    return j;
+}
+
+// Swap electrons 1 and 2 in place (the TRIPLET and PZ evaluations are written
+// for (A - a)(r1 - r2) <= 0 so that no exponential can overflow; the other
+// half-space follows from the exchange symmetry psi(2,1) = -psi(1,2) (TRIPLET)
+// or sym * psi(1,2) (PZ)).
+template <typename R>
+HD void swap_electrons(R y[6])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R t = y[k];
+        y[k] = y[3 + k];
+        y[3 + k] = t;
+    }
+}
+
+// Drift b = grad ln|psi|, local energy E_L = -(1/2) Lap(psi)/psi + V and the sign
+// of psi (0 on the node).  V = -Z/r1 - Z/r2 + ee/r12.
+template <typename R, int TRIAL>
+HD int trial_eval(const TrialParams<R>& p, const R y_in[6], R b[6], R& el)
+{
+    R y[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = y_in[k];
+    bool swapped = false;
+    if (has_node<TRIAL>::value) {
+        const R s1 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+        const R s2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
+        swapped = (p.A - p.a) * (s1 - s2) > (R)0;
+        if (swapped) swap_electrons(y);
+    }
+    Geo<R> g;
+    geometry(y, g);
+    int sign = 1;
+    if (TRIAL == TRIAL_EXPO) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            b[k] = -p.A * g.h1[k];
+            b[3 + k] = -p.A * g.h2[k];
+        }
+        // -A^2 + (A - Z)(1/r1 + 1/r2) + ee/r12: exactly -Z^2 for A = Z, ee = 0
+        el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + (p.ee != (R)0 ? p.ee * g.i12 : (R)0);
+    } else if (TRIAL == TRIAL_PADE) {
+        const Jas<R> j = jastrow(p, g);
+        R w = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            b[k] = -p.A * g.h1[k] + j.up * g.h12[k];
+            b[3 + k] = -p.A * g.h2[k] - j.up * g.h12[k];
+            w += (g.h1[k] - g.h2[k]) * g.h12[k];
+        }
+        el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + p.A * j.up * w - j.upp - j.up * j.up + j.ee_term;
+    } else if (TRIAL == TRIAL_TRIPLET) {
+        // Phi = e^{-A r1 - a r2} D, D = 1 - e^d = -expm1(d), d = (A - a)(r1 - r2) <= 0
+        const Jas<R> j = jastrow(p, g);
+        const R d = (p.A - p.a) * (g.r1 - g.r2);
+        const R em = m::expm1_(d);
+        const R D = -em;
+        const R q = (R)1 + em;
+        const R iD = m::rcp_(D);
+        const R g1 = (-p.A + p.a * q) * iD;
+        const R g2 = (-p.a + p.A * q) * iD;
+        const R l1 = ((p.A * p.A - (R)2 * p.A * g.i1) - q * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
+        const R l2 = ((p.a * p.a - (R)2 * p.a * g.i2) - q * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
+        R c1 = 0, c2 = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            b[k] = g1 * g.h1[k] + j.up * g.h12[k];
+            b[3 + k] = g2 * g.h2[k] - j.up * g.h12[k];
+            c1 += g.h1[k] * g.h12[k];
+            c2 += g.h2[k] * g.h12[k];
+        }
+        el = (R)-0.5 * (l1 + l2) - j.up * (g1 * c1 - g2 * c2) - j.upp - j.up * j.up + j.ee_term -
+             p.Z * (g.i1 + g.i2);
+        sign = (D > (R)0) ? 1 : 0;
+        if (swapped) sign = -sign;
+    } else {  // TRIAL_PZ: Phi = e^{-A r1 - a r2} P, P = z2 + sym z1 rho, rho = e^{(A - a)(r1 - r2)} <= 1
+        const Jas<R> j = jastrow(p, g);
+        const R rho = m::exp_((p.A - p.a) * (g.r1 - g.r2));
+        const R z1 = y[2], z2 = y[5];
+        const R sr = p.sym * rho;
+        const R P = z2 + sr * z1;
+        const R iP = m::rcp_(P);
+        const R k1 = p.A * z2 + sr * p.a * z1;  // grad_1 Phi/f = -k1 h1 + sr zhat
+        const R k2 = p.a * z2 + sr * p.A * z1;  // grad_2 Phi/f = zhat - k2 h2
+        R gp1[3], gp2[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            gp1[k] = -k1 * g.h1[k] * iP;
+            gp2[k] = -k2 * g.h2[k] * iP;
+        }
+        gp1[2] += sr * iP;
+        gp2[2] += iP;
+        const R l1 = (z2 * (p.A * p.A - (R)2 * p.A * g.i1) + sr * z1 * (p.a * p.a - (R)4 * p.a * g.i1)) * iP;
+        const R l2 = (z2 * (p.a * p.a - (R)4 * p.a * g.i2) + sr * z1 * (p.A * p.A - (R)2 * p.A * g.i2)) * iP;
+        R cr = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            b[k] = gp1[k] + j.up * g.h12[k];
+            b[3 + k] = gp2[k] - j.up * g.h12[k];
+            cr += (gp1[k] - gp2[k]) * g.h12[k];
+        }
+        el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        sign = (P > (R)0) ? 1 : ((P < (R)0) ? -1 : 0);
+        if (swapped && p.sym < (R)0) sign = -sign;
+    }
+    if (swapped) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const R t = b[k];
+            b[k] = b[3 + k];
+            b[3 + k] = t;
+        }
+    }
+    return sign;
+}
+
+// ln|psi| (binary64; -inf on the node), for the Metropolis start.
+template <int TRIAL>
+HD double trial_lnpsi(const TrialParams<double>& p, const double y_in[6])
+{
+    double y[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = y_in[k];
+    if (has_node<TRIAL>::value) {
+        const double s1 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+        const double s2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
+        if ((p.A - p.a) * (s1 - s2) > 0.0) swap_electrons(y);
+    }
+    const double r1 = ::sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    const double r2 = ::sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+    const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
+    const double r12 = ::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double U = (TRIAL == TRIAL_EXPO) ? 0.0 : p.c * r12 / (1.0 + p.beta * r12);
+    if (TRIAL == TRIAL_EXPO || TRIAL == TRIAL_PADE) return -p.A * (r1 + r2) + U;
+    if (TRIAL == TRIAL_TRIPLET) {
+        const double D = -::expm1((p.A - p.a) * (r1 - r2));
+        return -p.A * r1 - p.a * r2 + ::log(::fabs(D)) + U;
+    }
+    const double rho = ::exp((p.A - p.a) * (r1 - r2));
+    const double P = y[5] + p.sym * y[2] * rho;
+    return -p.A * r1 - p.a * r2 + ::log(::fabs(P)) + U;
+}
+
+// Start position of one walker: Y = init_sigma xi(phase 0, vector 0), then
+// n_met Metropolis steps on |psi|^2 with proposal width sigma_m (binary64).
+template <int TRIAL>
+HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, double init_sigma,
+                    double sigma_m, double y[6])
+{
+    double xi[6];
+    gauss6_c1<double>(st, PHASE_INIT, 0u, xi, nullptr);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = init_sigma * xi[k];
+    double lp = trial_lnpsi<TRIAL>(tp, y);
+    for (int mstep = 0; mstep < n_met; ++mstep) {
+        double u, yt[6];
+        gauss6_c1<double>(st, PHASE_METROPOLIS, (uint32_t)mstep, xi, &u);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) yt[k] = y[k] + sigma_m * xi[k];
+        const double lpt = trial_lnpsi<TRIAL>(tp, yt);
+        if (::log(u) < 2.0 * (lpt - lp)) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) y[k] = yt[k];
+            lp = lpt;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One walker: state and one step of the discretised drifted diffusion.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct WalkerState {
+    R y[6];
+    R b[6];
+    R el;
+    int sign;
+    double lnw;
+};
+
+struct StepConst {
+    double dt, half_dt, e_ref;
+    int quad_right;
+};
+
+template <typename R, int TRIAL>
+HD void walker_reset(const TrialParams<R>& tp, WalkerState<R>& w)
+{
+    w.sign = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el);
+}
+
+// Y' = Y + dt b + sqrt(dt) xi; node crossing absorbs (lnw = -inf, frozen);
+// otherwise the quadrature updates ln w in binary64.
+template <typename R, int TRIAL>
+HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, R dt_r, R sqdt_r, const R xi[6],
+                    WalkerState<R>& w)
+{
+    if (w.lnw == -INFINITY) return;
+    R yt[6], bt[6], elt;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) yt[k] = w.y[k] + dt_r * w.b[k] + sqdt_r * xi[k];
+    const int st = trial_eval<R, TRIAL>(tp, yt, bt, elt);
+    if (has_node<TRIAL>::value && (st != w.sign || st == 0)) {
+        w.lnw = -INFINITY;
+        return;
+    }
+    const double en = (double)elt - sc.e_ref;
+    double lw;
+    if (sc.quad_right)
+        lw = w.lnw - sc.dt * en;
+    else
+        lw = w.lnw - sc.half_dt * (((double)w.el - sc.e_ref) + en);
+    if (!__builtin_isfinite((double)elt)) lw = NAN;
+    w.lnw = lw;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        w.y[k] = yt[k];
+        w.b[k] = bt[k];
+    }
+    w.el = elt;
+    w.sign = st;
+}
+
+}  // namespace hefk

@@ -1,0 +1,404 @@
+// hefk_kernels.hip -- gfx950 kernels and the C ABI entry points of libhefk
+// (start ensemble, persistent walker propagation with a log-domain space
+// average at sampling times, deterministic merge of block partials).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <cmath>
+
+#include "he_fk.h"
+#include "hefk_device.hpp"
+#include "hefk_reduce.hpp"
+
+namespace hefk {
+
+constexpr int kBlock = 256;  // 4 waves of 64 lanes; one walker per lane
+
+struct KArgs {
+    TrialParams<double> tpd;
+    TrialParams<float> tpf;
+    StepConst sc;
+    double dt, sqdt;
+    float dtf, sqdtf;
+    double init_sigma, metropolis_sigma;
+    uint32_t key0, key1;
+    uint64_t walker_offset;
+    int64_t n;
+    int32_t n_metropolis;
+    int32_t step0, n_steps, sample_every, n_samples, ckpt_every;
+    void* x;
+    double* lnw;
+    void* el;
+    double* partials;  // [gridDim.x][n_samples][8]
+    double* ckpt;      // [n_ckpt][7][n] or null
+};
+
+template <typename R>
+__device__ __forceinline__ const TrialParams<R>& tparams(const KArgs& a);
+template <>
+__device__ __forceinline__ const TrialParams<double>& tparams<double>(const KArgs& a)
+{
+    return a.tpd;
+}
+template <>
+__device__ __forceinline__ const TrialParams<float>& tparams<float>(const KArgs& a)
+{
+    return a.tpf;
+}
+
+__device__ __forceinline__ Stream make_stream(const KArgs& a, int64_t i)
+{
+    const uint64_t g = a.walker_offset + (uint64_t)i;
+    Stream s;
+    s.k0 = a.key0;
+    s.k1 = a.key1;
+    s.g0 = (uint32_t)g;
+    s.g1 = (uint32_t)(g >> 32);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Start ensemble: Gaussian draw, Metropolis on |psi|^2 (binary64), then the
+// local energy at the stored (possibly binary32) position.
+// ---------------------------------------------------------------------------
+template <typename R, int TRIAL>
+__global__ __launch_bounds__(kBlock) void init_kernel(const KArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n) return;
+    const Stream st = make_stream(a, i);
+    double y[6];
+    init_walker<TRIAL>(a.tpd, st, a.n_metropolis, a.init_sigma, a.metropolis_sigma, y);
+    R yr[6], b[6], el;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) yr[k] = (R)y[k];
+    trial_eval<R, TRIAL>(tparams<R>(a), yr, b, el);
+    R* x = (R*)a.x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[(int64_t)k * a.n + i] = yr[k];
+    ((R*)a.el)[i] = el;
+    a.lnw[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent propagation.  Each block walks over chunks of 256 walkers
+// (chunk c = blockIdx.x + j * gridDim.x); each lane keeps its walker in
+// registers for all n_steps steps.  At every sampling time the block reduces
+// (max ln w, then S0, S1, S2 and counts) and merges the result into its own
+// partial row in the workspace.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void sample_row(const KArgs& a, double* part_row, bool first, bool valid,
+                                           const WalkerState<R>& w, double* red)
+{
+    Tuple t = block_tuple(valid, w.lnw, (double)w.el, red);
+    if (threadIdx.x == 0) {
+        if (!first) t = merge_tuple(load_tuple(part_row), t);
+        store_tuple(part_row, t);
+    }
+}
+
+template <typename R, int TRIAL, int NOISE>
+__global__ __launch_bounds__(kBlock) void propagate_kernel(const KArgs a)
+{
+    __shared__ double red[kRedSlots];
+    const TrialParams<R>& tp = tparams<R>(a);
+    const R dt_r = (sizeof(R) == 8) ? (R)a.dt : (R)a.dtf;
+    const R sqdt_r = (sizeof(R) == 8) ? (R)a.sqdt : (R)a.sqdtf;
+    const int64_t n = a.n;
+    const int64_t n_chunks = (n + kBlock - 1) / kBlock;
+    double* part = a.partials + (size_t)blockIdx.x * (size_t)a.n_samples * 8;
+    R* x = (R*)a.x;
+
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const bool first = (c == (int64_t)blockIdx.x);
+        const int64_t i = c * kBlock + threadIdx.x;
+        const bool valid = i < n;
+        const int64_t ii = valid ? i : n - 1;  // tail lanes shadow the last walker, never stored or counted
+        const Stream st = make_stream(a, ii);
+        WalkerState<R> w;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w.y[k] = x[(int64_t)k * n + ii];
+        w.lnw = a.lnw[ii];
+        walker_reset<R, TRIAL>(tp, w);
+
+        sample_row<R>(a, part, first, valid, w, red);
+        if (a.ckpt && valid) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a.ckpt[(int64_t)k * n + i] = (double)w.y[k];
+            a.ckpt[6 * n + i] = w.lnw;
+        }
+
+        int row = 1, until_sample = a.sample_every, until_ckpt = a.ckpt_every, crow = 1;
+        NoiseGen<R, NOISE> noise;
+        for (int k = 0; k < a.n_steps; ++k) {
+            R xi[6];
+            noise.draw(st, (uint32_t)(a.step0 + k), xi);
+            walker_step<R, TRIAL>(tp, a.sc, dt_r, sqdt_r, xi, w);
+            if (--until_sample == 0) {
+                until_sample = a.sample_every;
+                sample_row<R>(a, part + (size_t)row * 8, first, valid, w, red);
+                ++row;
+            }
+            if (a.ckpt && --until_ckpt == 0) {
+                until_ckpt = a.ckpt_every;
+                if (valid) {
+                    double* cp = a.ckpt + (size_t)crow * 7 * (size_t)n;
+#pragma unroll
+                    for (int kk = 0; kk < 6; ++kk) cp[(int64_t)kk * n + i] = (double)w.y[kk];
+                    cp[6 * n + i] = w.lnw;
+                }
+                ++crow;
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) x[(int64_t)k * n + i] = w.y[k];
+            a.lnw[i] = w.lnw;
+            ((R*)a.el)[i] = w.el;
+        }
+    }
+}
+
+// Merge the per-block partial rows of one sample (blockIdx.x) in a fixed order.
+__global__ __launch_bounds__(kBlock) void merge_kernel(const double* __restrict__ partials, int n_parts,
+                                                       int n_samples, double* __restrict__ samples)
+{
+    __shared__ double sh[kBlock * 8];
+    const int s = blockIdx.x;
+    Tuple t = empty_tuple();
+    for (int b = threadIdx.x; b < n_parts; b += kBlock)
+        t = merge_tuple(t, load_tuple(partials + ((size_t)b * n_samples + s) * 8));
+    store_tuple(sh + threadIdx.x * 8, t);
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            Tuple l = load_tuple(sh + threadIdx.x * 8);
+            Tuple r = load_tuple(sh + (threadIdx.x + w) * 8);
+            store_tuple(sh + threadIdx.x * 8, merge_tuple(l, r));
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) store_tuple(samples + (size_t)s * 8, load_tuple(sh));
+}
+
+// ---------------------------------------------------------------------------
+// Host side: argument checks, kernel choice, launch geometry.
+// ---------------------------------------------------------------------------
+typedef void (*KernelFn)(KArgs);
+
+template <typename R, int TRIAL>
+KernelFn pick_propagate(int noise)
+{
+    switch (noise) {
+        case NOISE_G1: return propagate_kernel<R, TRIAL, NOISE_G1>;
+        case NOISE_G2: return propagate_kernel<R, TRIAL, NOISE_G2>;
+        default: return propagate_kernel<R, TRIAL, NOISE_PM1>;
+    }
+}
+
+template <typename R>
+KernelFn pick_propagate_r(int trial, int noise)
+{
+    switch (trial) {
+        case TRIAL_EXPO: return pick_propagate<R, TRIAL_EXPO>(noise);
+        case TRIAL_PADE: return pick_propagate<R, TRIAL_PADE>(noise);
+        case TRIAL_TRIPLET: return pick_propagate<R, TRIAL_TRIPLET>(noise);
+        default: return pick_propagate<R, TRIAL_PZ>(noise);
+    }
+}
+
+template <typename R>
+KernelFn pick_init_r(int trial)
+{
+    switch (trial) {
+        case TRIAL_EXPO: return init_kernel<R, TRIAL_EXPO>;
+        case TRIAL_PADE: return init_kernel<R, TRIAL_PADE>;
+        case TRIAL_TRIPLET: return init_kernel<R, TRIAL_TRIPLET>;
+        default: return init_kernel<R, TRIAL_PZ>;
+    }
+}
+
+static int noise_kind(const he_fk_params* p)
+{
+    if (p->noise == HE_FK_NOISE_PM1) return NOISE_PM1;
+    return p->contract == 2 ? NOISE_G2 : NOISE_G1;
+}
+
+static KernelFn propagate_fn(const he_fk_params* p)
+{
+    return p->precision == HE_FK_MIXED ? pick_propagate_r<float>(p->trial, noise_kind(p))
+                                       : pick_propagate_r<double>(p->trial, noise_kind(p));
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_params(const he_fk_params* p)
+{
+    if (!p) return HE_FK_EINVAL;
+    if (p->trial < HE_FK_TRIAL_EXPO || p->trial > HE_FK_TRIAL_PZ) return HE_FK_EINVAL;
+    if (p->trial == HE_FK_TRIAL_PZ && p->sym != 1 && p->sym != -1) return HE_FK_EINVAL;
+    if (p->ee != 0 && p->ee != 1) return HE_FK_EINVAL;
+    if (p->noise != HE_FK_NOISE_GAUSS && p->noise != HE_FK_NOISE_PM1) return HE_FK_EINVAL;
+    if (p->quad != HE_FK_QUAD_TRAPEZOID && p->quad != HE_FK_QUAD_RIGHT) return HE_FK_EINVAL;
+    if (p->contract != 1 && p->contract != 2) return HE_FK_EINVAL;
+    if (p->precision != HE_FK_FP64 && p->precision != HE_FK_MIXED) return HE_FK_EINVAL;
+    if (p->n_metropolis < 0) return HE_FK_EINVAL;
+    if (!finite_pos(p->Z) || !finite_pos(p->dt) || !finite_pos(p->metropolis_sigma) ||
+        !finite_pos(p->init_sigma) || !std::isfinite(p->e_ref))
+        return HE_FK_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(p->theta[k])) return HE_FK_EINVAL;
+    if (!(p->theta[0] > 0.0)) return HE_FK_EINVAL;
+    if (p->trial != HE_FK_TRIAL_EXPO && !(p->theta[1] >= 0.0)) return HE_FK_EINVAL;
+    if (p->n_walkers < 1 || p->n_walkers > (int64_t(1) << 40)) return HE_FK_EINVAL;
+    if (p->walker_offset > UINT64_MAX - (uint64_t)p->n_walkers) return HE_FK_EINVAL;
+    return HE_FK_OK;
+}
+
+static KArgs make_args(const he_fk_params* p)
+{
+    KArgs a;
+    memset(&a, 0, sizeof(a));
+    a.tpd.A = p->theta[0];
+    a.tpd.beta = p->theta[1];
+    a.tpd.c = p->theta[2];
+    a.tpd.a = p->theta[3];
+    a.tpd.Z = p->Z;
+    a.tpd.ee = (double)p->ee;
+    a.tpd.sym = (double)(p->trial == HE_FK_TRIAL_PZ ? p->sym : 1);
+    a.tpf.A = (float)a.tpd.A;
+    a.tpf.beta = (float)a.tpd.beta;
+    a.tpf.c = (float)a.tpd.c;
+    a.tpf.a = (float)a.tpd.a;
+    a.tpf.Z = (float)a.tpd.Z;
+    a.tpf.ee = (float)a.tpd.ee;
+    a.tpf.sym = (float)a.tpd.sym;
+    a.sc.dt = p->dt;
+    a.sc.half_dt = 0.5 * p->dt;
+    a.sc.e_ref = p->e_ref;
+    a.sc.quad_right = (p->quad == HE_FK_QUAD_RIGHT);
+    a.dt = p->dt;
+    a.sqdt = std::sqrt(p->dt);
+    a.dtf = (float)p->dt;
+    a.sqdtf = (float)std::sqrt(p->dt);
+    a.init_sigma = p->init_sigma;
+    a.metropolis_sigma = p->metropolis_sigma;
+    a.key0 = (uint32_t)p->seed;
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.walker_offset = p->walker_offset;
+    a.n = p->n_walkers;
+    a.n_metropolis = p->n_metropolis;
+    return a;
+}
+
+// Blocks of a propagate launch: every block resident at once, none without a chunk.
+static int propagate_grid(const he_fk_params* p, int64_t* out)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HE_FK_EDEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return HE_FK_EDEVICE;
+    KernelFn fn = propagate_fn(p);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
+        return HE_FK_EDEVICE;
+    if (per_cu < 1) per_cu = 1;
+    const int64_t n_chunks = (p->n_walkers + kBlock - 1) / kBlock;
+    int64_t g = (int64_t)cus * per_cu;
+    if (g > n_chunks) g = n_chunks;
+    // same number of chunks per block for as many blocks as possible
+    const int64_t per_block = (n_chunks + g - 1) / g;
+    g = (n_chunks + per_block - 1) / per_block;
+    *out = g;
+    return HE_FK_OK;
+}
+
+static int check_steps(int64_t step0, int64_t n_steps, int32_t sample_every)
+{
+    if (step0 < 0 || n_steps < 0 || sample_every < 1) return HE_FK_EINVAL;
+    if (n_steps % sample_every != 0) return HE_FK_EINVAL;
+    if (step0 + n_steps >= (int64_t(1) << 31)) return HE_FK_EINVAL;
+    return HE_FK_OK;
+}
+
+}  // namespace hefk
+
+using namespace hefk;
+
+extern "C" {
+
+int he_fk_init(const he_fk_params* p, const he_fk_walkers* w, void* stream)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!w || !w->x || !w->lnw || !w->el) return HE_FK_EINVAL;
+    KArgs a = make_args(p);
+    a.x = w->x;
+    a.lnw = w->lnw;
+    a.el = w->el;
+    KernelFn fn = p->precision == HE_FK_MIXED ? pick_init_r<float>(p->trial) : pick_init_r<double>(p->trial);
+    const int64_t blocks = (p->n_walkers + kBlock - 1) / kBlock;
+    if (blocks > INT32_MAX) return HE_FK_EINVAL;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? HE_FK_OK : HE_FK_EDEVICE;
+}
+
+size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, int32_t sample_every)
+{
+    if (check_params(p) || check_steps(0, n_steps, sample_every)) return 0;
+    int64_t g = 0;
+    if (propagate_grid(p, &g)) return 0;
+    return (size_t)g * (size_t)(n_steps / sample_every + 1) * 8 * sizeof(double);
+}
+
+int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,
+                    int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every, void* workspace,
+                    size_t workspace_bytes, void* stream)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    rc = check_steps(step0, n_steps, sample_every);
+    if (rc) return rc;
+    if (!w || !w->x || !w->lnw || !w->el || !samples || !workspace) return HE_FK_EINVAL;
+    if (ckpt) {
+        if (p->precision != HE_FK_FP64 || ckpt_every < 1 || n_steps % ckpt_every != 0) return HE_FK_EINVAL;
+    }
+    int64_t g = 0;
+    rc = propagate_grid(p, &g);
+    if (rc) return rc;
+    const int64_t n_samples = n_steps / sample_every + 1;
+    const size_t need = (size_t)g * (size_t)n_samples * 8 * sizeof(double);
+    if (workspace_bytes < need) return HE_FK_ESCRATCH;
+    KArgs a = make_args(p);
+    a.x = w->x;
+    a.lnw = w->lnw;
+    a.el = w->el;
+    a.step0 = (int32_t)step0;
+    a.n_steps = (int32_t)n_steps;
+    a.sample_every = sample_every;
+    a.n_samples = (int32_t)n_samples;
+    a.ckpt_every = ckpt ? ckpt_every : 0;
+    a.ckpt = ckpt;
+    a.partials = (double*)workspace;
+    hipLaunchKernelGGL(propagate_fn(p), dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a);
+    if (hipGetLastError() != hipSuccess) return HE_FK_EDEVICE;
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)n_samples), dim3(kBlock), 0, (hipStream_t)stream,
+                       (const double*)workspace, (int)g, (int)n_samples, samples);
+    return hipGetLastError() == hipSuccess ? HE_FK_OK : HE_FK_EDEVICE;
+}
+
+const char* he_fk_strerror(int code)
+{
+    switch (code) {
+        case HE_FK_OK: return "ok";
+        case HE_FK_EINVAL: return "invalid argument";
+        case HE_FK_EDEVICE: return "HIP device error";
+        case HE_FK_ENONFINITE: return "non-finite ln w or local energy in a sample row";
+        case HE_FK_EALLDEAD: return "no live walker in a sample row";
+        case HE_FK_ESCRATCH: return "workspace or scratch too small";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+"""CPU tests of the product's host logic: the C ABI loads and exports every
+declared symbol, argument checks, the host energy estimators against the
+oracle's, and a host build of the kernels' per-walker arithmetic against the
+oracle (same Philox streams)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import estimators as est
+from paper_1703_08977_amd import _lib, api
+from paper_1703_08977_amd import workloads as W
+
+from hefk_testutil import ROOT, host_run
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "he_fk.h")).read()
+    names = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(he_fk_\w+)\s*\(", hdr, flags=re.M))
+    assert names == set(_lib.EXPORTS)
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror():
+    for c in (0, -1, -2, -3, -4, -5):
+        assert _lib.strerror(c)
+    assert _lib.strerror(-99) == "unknown error"
+
+
+def _bad_params():
+    base = W.get("he_1s_expo_4k")
+    yield api.make_params(base, dt=-0.1)
+    yield api.make_params(base, dt=float("nan"))
+    yield api.make_params(base, n_walkers=0)
+    yield api.make_params(base, theta=[0.0])
+    yield api.make_params(base, Z=0.0)
+    yield api.make_params(base, metropolis_sigma=0.0)
+    p = api.make_params(base)
+    p.trial = 7
+    yield p
+    p = api.make_params(W.get("he_2P_pz_16m"))
+    p.sym = 0
+    yield p
+    p = api.make_params(base)
+    p.contract = 3
+    yield p
+    p = api.make_params(base)
+    p.walker_offset = (1 << 64) - 10
+    yield p
+
+
+def test_invalid_params_rejected_before_any_launch():
+    w = _lib.HeFkWalkers(1, 1, 1)  # never dereferenced: the checks come first
+    for p in _bad_params():
+        assert _lib.lib().he_fk_init(ctypes.byref(p), ctypes.byref(w), None) == _lib.HE_FK_EINVAL
+        assert _lib.lib().he_fk_propagate_workspace_bytes(ctypes.byref(p), 10, 5) == 0
+    p = api.make_params(W.get("he_1s_expo_4k"))
+    assert _lib.lib().he_fk_init(ctypes.byref(p), None, None) == _lib.HE_FK_EINVAL
+    z = _lib.HeFkWalkers(0, 0, 0)
+    assert _lib.lib().he_fk_init(ctypes.byref(p), ctypes.byref(z), None) == _lib.HE_FK_EINVAL
+    # step arguments: n_steps not a multiple of sample_every, negative steps
+    for (s0, ns, se) in ((0, 10, 3), (-1, 10, 5), (0, -5, 5), (0, 10, 0), (2**31 - 5, 10, 5)):
+        rc = _lib.lib().he_fk_propagate(ctypes.byref(p), ctypes.byref(w), s0, ns, se, ctypes.c_void_p(1),
+                                        None, 0, ctypes.c_void_p(1), ctypes.c_size_t(1 << 30), None)
+        assert rc == _lib.HE_FK_EINVAL
+
+
+def _random_rows(rng, n, N=1000, dead_row=None, bad_row=None):
+    s = np.zeros((n, 8))
+    t = np.arange(n) * 0.05
+    s[:, 0] = -0.1 * t + 0.01 * rng.normal(size=n) + 3.0
+    s[:, 1] = rng.uniform(50, 100, size=n)
+    s[:, 2] = -2.9 * s[:, 1] * (1 + 0.01 * rng.normal(size=n))
+    s[:, 3] = s[:, 1] * rng.uniform(1, 5, size=n)
+    s[:, 4] = N
+    s[:, 6] = N
+    if dead_row is not None:
+        s[dead_row, 4] = 0
+    if bad_row is not None:
+        s[bad_row, 5] = 2
+    return s
+
+
+@pytest.mark.parametrize("n", [3, 4, 41, 121, 600])
+def test_energy_estimators_match_oracle(n):
+    rng = np.random.default_rng(n)
+    s = _random_rows(rng, n)
+    e_ref, dts = -2.9, 0.05
+    out, aux, rc = api.he_fk_energy(s, dts, e_ref, "fd")
+    assert rc == 0
+    assert np.abs(out - est.e_fd(s, dts, e_ref)).max() < 1e-12
+    assert np.abs(aux[:, 0] - est.log_mean_weight(s)).max() < 1e-14
+    assert np.abs(aux[:, 1] - est.ess(s)).max() < 1e-9
+    out, _, _ = api.he_fk_energy(s, dts, e_ref, "window")
+    assert abs(out[0] - est.e_window(s, dts, e_ref)) < 1e-10
+    out, _, _ = api.he_fk_energy(s, dts, e_ref, "fit")
+    Ef, a = est.e_fit(s, dts, e_ref)
+    assert abs(out[0] - Ef) < 1e-10 and abs(out[1] - a) < 1e-10
+    w = rng.uniform(0.5, 2.0, size=n)
+    out, _, _ = api.he_fk_energy(s, dts, e_ref, "fit", fit_w=w)
+    Ef, a = est.e_fit(s, dts, e_ref, w=w)
+    assert abs(out[0] - Ef) < 1e-10
+    out, _, _ = api.he_fk_energy(s, dts, e_ref, "mixed")
+    assert np.abs(out - est.e_mixed(s)).max() < 1e-14
+
+
+@pytest.mark.parametrize("name,tol", [("paper_table3.txt", 1e-6), ("paper_table4.txt", 1e-6)])
+def test_energy_fit_reproduces_paper_tables(name, tol):
+    rows, lam = [], {}
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        if line.startswith("# lambda0"):
+            parts = line.replace("#", "").split()
+            lam = {"l0": float(parts[2]), "l1": float(parts[5])}
+        elif line.strip() and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+    tab = np.array(rows)
+    L = np.concatenate([[0.0], tab[:, 0] * tab[:, 5]])  # t * (ls-fit column), t = 0, 8, ..., 48
+    N = 150000
+    s = np.zeros((len(L), 8))
+    s[:, 0] = L + math.log(N)
+    s[:, 1] = 1.0
+    s[:, 3] = 1.0
+    s[:, 4] = N
+    s[:, 6] = N
+    out, _, rc = api.he_fk_energy(s, 8.0, lam["l0"], "fit")
+    assert rc == 0 and abs(out[0] - lam["l1"]) < tol
+
+
+def test_energy_error_codes():
+    rng = np.random.default_rng(3)
+    s = _random_rows(rng, 10, dead_row=4)
+    _, aux, rc = api.he_fk_energy(s, 0.05, -2.9, "fd", raise_on_error=False)
+    assert rc == _lib.HE_FK_EALLDEAD and np.isfinite(aux[0, 0])
+    s = _random_rows(rng, 10, bad_row=7, dead_row=2)
+    _, _, rc = api.he_fk_energy(s, 0.05, -2.9, "fd", raise_on_error=False)
+    assert rc == _lib.HE_FK_ENONFINITE
+    s = _random_rows(rng, 10)
+    for args in ((0.0, "fd"), (float("inf"), "fd")):
+        _, _, rc = api.he_fk_energy(s, args[0], -2.9, args[1], raise_on_error=False)
+        assert rc == _lib.HE_FK_EINVAL
+    _, _, rc = api.he_fk_energy(s[:2], 0.05, -2.9, "fit", raise_on_error=False)
+    assert rc == _lib.HE_FK_EINVAL
+    s[3, 6] = 0
+    _, _, rc = api.he_fk_energy(s, 0.05, -2.9, "fd", raise_on_error=False)
+    assert rc == _lib.HE_FK_EINVAL
+
+
+# --------------------------------------------------------------------------
+# Host build of the kernels' per-walker code against the oracle (binary64).
+# --------------------------------------------------------------------------
+
+HOST_CASES = [
+    ("he_1s_expo_4k", {}),
+    ("he_1s_pade_1m", {}),
+    ("he_1s_pade_1m", {"noise": "pm1"}),
+    ("he_1s_pade_1m", {"contract": 2}),
+    ("he_1s_pade_1m", {"quad": "right"}),
+    ("he_2tripS_4m", {"dt": 0.005}),
+    ("he_2P_pz_16m", {"dt": 0.005}),
+    ("he_2P_pz_16m", {"dt": 0.005, "sym": -1, "theta": [2.0, 0.3, 0.25, 0.5], "noise": "pm1"}),
+    ("hydrogen", {}),
+]
+
+
+@pytest.mark.parametrize("name,over", HOST_CASES, ids=lambda v: str(v))
+def test_kernel_arithmetic_host_build_matches_oracle(name, over):
+    cfg = W.get(name, **over)
+    ids = np.arange(48) * 13 + 1
+    h = host_run(cfg, ids, 300, 20)
+    r = oracle.run(cfg, ids, 300, 20)
+    assert np.abs(h["x0"] - r["x0"]).max() < 1e-13
+    assert np.array_equal(np.isfinite(h["lnw"]), np.isfinite(r["lnw"]))
+    f = np.isfinite(r["ell"])
+    assert np.array_equal(f, np.isfinite(h["ell"]))
+    assert np.abs(h["ell"][f] - r["ell"][f]).max() < 1e-12
+    alive = np.isfinite(r["lnw"])
+    assert np.abs(h["x"][alive] - r["x"][alive]).max() < 1e-12
