@@ -20,6 +20,10 @@ def hipcc() -> str:
 
 def flags():
     return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+            # fuse multiply-adds only inside one source expression: the fused / unfused
+            # choice then does not depend on the inlining context, so a propagation resumed
+            # from stored walkers is bitwise the same as an uninterrupted one
+            "-ffp-contract=on",
             # packed FP32 arithmetic stays off (v_pk_* forms are avoided on this target)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", HERE]
