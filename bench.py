@@ -35,7 +35,21 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 steps for the speedup (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16384)
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
+                    help="copy: a plain 1 GiB device copy, three times (the reference reading of the HBM "
+                         "byte counters FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def copy_reference():
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_per_copy": nbytes, "copies": 3}), flush=True)
 
 
 def run_leg(cfg, n_steps_timed, n_warmup, seeds):
@@ -104,6 +118,9 @@ def cpu_baseline(cfg, n_walkers):
 
 def main():
     args = parse()
+    if args.mode == "copy":
+        copy_reference()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "
               "reduction, and this build measures one MI355X (requested --gpus %d)" % args.gpus, file=sys.stderr)

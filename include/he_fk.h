@@ -100,6 +100,14 @@ typedef struct {
     double e_ref;         /* trial energy lambda0 of eq. (4); shifts ln w, cancels in E */
     double metropolis_sigma; /* Metropolis proposal width (> 0) */
     double init_sigma;    /* width of the Gaussian the Metropolis chain starts from (> 0) */
+    /* drift_limit = a >= 0.  a = 0: the plain discretisation.  a > 0: near the
+       singular points of b and E_L (the node of an inexact trial function)
+       the drift and the integrand are limited by f = 2 / (1 + sqrt(1 + 2 a dt |b|^2))
+       (Umrigar, Nightingale, Runge, J. Chem. Phys. 99, 2865 (1993)):
+       Y' = Y + dt f b + sqrt(dt) xi and E_L - e_ref -> f (E_L - e_ref).  f -> 1
+       as dt -> 0, so the limit dt -> 0 is unchanged; it keeps a walker that lands
+       next to the node from taking an unbounded weight in one step. */
+    double drift_limit;
     uint64_t seed;        /* Philox key */
     uint64_t walker_offset; /* global id of walker 0 of this call (shards of one ensemble) */
     int64_t n_walkers;    /* N >= 1 */

@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
         ("n_metropolis", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("Z", ctypes.c_double), ("theta", ctypes.c_double * 4), ("dt", ctypes.c_double),
         ("e_ref", ctypes.c_double), ("metropolis_sigma", ctypes.c_double),
-        ("init_sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("init_sigma", ctypes.c_double), ("drift_limit", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -111,6 +111,7 @@ def params(cfg: dict) -> _Params:
     p.e_ref = float(cfg.get("e_ref", 0.0))
     p.metropolis_sigma = float(cfg.get("metropolis_sigma", 0.5))
     p.init_sigma = float(cfg.get("init_sigma", 1.0))
+    p.drift_limit = float(cfg.get("drift_limit", 0.0))
     p.seed = int(cfg.get("seed", 0)) & ((1 << 64) - 1)
     return p
 

@@ -75,6 +75,7 @@ typedef struct {
     double e_ref;         /* the trial energy lambda0 used as the shift in eq. (4) */
     double metropolis_sigma;
     double init_sigma;
+    double drift_limit;   /* a >= 0: drift / integrand limiting near singular points, 0 = off */
     uint64_t seed;
 } ofk_params;
 
@@ -365,6 +366,23 @@ static void noise6(const ofk_params* p, uint64_t k, uint64_t g, double xi[6])
 }
 
 /*
+ * Limiting of the drift and of the integrand near the singular points of an
+ * inexact trial function (Umrigar, Nightingale, Runge, J. Chem. Phys. 99, 2865
+ * (1993)): with x = a dt |b|^2 the drift b becomes f b and E_L - e_ref becomes
+ * f (E_L - e_ref), f = (sqrt(1 + 2x) - 1) / x, evaluated here in the equivalent
+ * form 2 / (1 + sqrt(1 + 2x)), which has no cancellation for small x.  f = 1 when
+ * the limiting is off (a = 0) and f -> 1 as dt -> 0.
+ */
+static double limit_factor(const ofk_params* p, const double b[6])
+{
+    if (!(p->drift_limit > 0.0)) return 1.0;
+    double v2 = 0.0;
+    for (int j = 0; j < 6; ++j) v2 += b[j] * b[j];
+    double x = p->drift_limit * p->dt * v2;
+    return 2.0 / (1.0 + sqrt(1.0 + 2.0 * x));
+}
+
+/*
  * State: y[6] and lnw.  lnw = -inf marks a walker absorbed at the node; a NaN
  * marks a walker whose local energy went non-finite (kept NaN from then on).
  * Per step: Y' = Y + dt b(Y) + sqrt(dt) xi_k; if the trial has a node and
@@ -380,6 +398,8 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
 {
     ofk_eval cur;
     ofk_trial_eval(p, y, &cur);
+    double f = limit_factor(p, cur.b);
+    double eb = f * (cur.el - p->e_ref); /* integrand at the current position */
     double w = *lnw;
     double sqdt = sqrt(p->dt);
     int node = trial_has_node(p);
@@ -392,19 +412,23 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
         if (live) {
             double xi[6], yt[6];
             noise6(p, (uint64_t)(step0 + k), g, xi);
-            for (int j = 0; j < 6; ++j) yt[j] = y[j] + p->dt * cur.b[j] + sqdt * xi[j];
+            for (int j = 0; j < 6; ++j) yt[j] = y[j] + p->dt * (f * cur.b[j]) + sqdt * xi[j];
             ofk_eval nxt;
             ofk_trial_eval(p, yt, &nxt);
             if (node && (nxt.sign != cur.sign || nxt.sign == 0)) {
                 w = -INFINITY;
             } else {
+                double fn = limit_factor(p, nxt.b);
+                double ebn = fn * (nxt.el - p->e_ref);
                 if (p->quad == OFK_QUAD_RIGHT)
-                    w = w - p->dt * (nxt.el - p->e_ref);
+                    w = w - p->dt * ebn;
                 else
-                    w = w - (0.5 * p->dt) * ((cur.el - p->e_ref) + (nxt.el - p->e_ref));
+                    w = w - (0.5 * p->dt) * (eb + ebn);
                 if (!isfinite(nxt.el)) w = NAN;
                 memcpy(y, yt, sizeof(double) * 6);
                 cur = nxt;
+                f = fn;
+                eb = ebn;
             }
         }
         if (sample_every > 0 && (k + 1) % sample_every == 0) {
@@ -532,6 +556,15 @@ static void pade_eval_c(const ofk_params* p, cplx alpha, cplx beta, const cplx y
     *el = -0.5 * lap_total + V;
 }
 
+static cplx limit_factor_c(const ofk_params* p, const cplx b[6])
+{
+    if (!(p->drift_limit > 0.0)) return 1.0;
+    cplx v2 = 0.0;
+    for (int j = 0; j < 6; ++j) v2 += b[j] * b[j];
+    cplx x = p->drift_limit * p->dt * v2;
+    return 2.0 / (1.0 + csqrt(1.0 + 2.0 * x));
+}
+
 /*
  * For walker g starting at y0 (fixed), propagate n_steps from step 0 with
  * parameter direction `dir` (0: alpha, 1: beta) perturbed by i h.  Writes
@@ -548,6 +581,8 @@ int ofk_dlnw_dtheta_walker(const ofk_params* p, uint64_t g, const double y0[6], 
     cplx y[6], b[6], el;
     for (int j = 0; j < 6; ++j) y[j] = y0[j];
     pade_eval_c(p, alpha, beta, y, b, &el);
+    cplx f = limit_factor_c(p, b);
+    cplx eb = f * (el - p->e_ref);
     cplx w = 0.0;
     double sqdt = sqrt(p->dt);
     int64_t s = 0;
@@ -556,17 +591,21 @@ int ofk_dlnw_dtheta_walker(const ofk_params* p, uint64_t g, const double y0[6], 
         double xi[6];
         noise6(p, (uint64_t)k, g, xi);
         cplx yt[6], bt[6], elt;
-        for (int j = 0; j < 6; ++j) yt[j] = y[j] + p->dt * b[j] + sqdt * xi[j];
+        for (int j = 0; j < 6; ++j) yt[j] = y[j] + p->dt * (f * b[j]) + sqdt * xi[j];
         pade_eval_c(p, alpha, beta, yt, bt, &elt);
+        cplx fn = limit_factor_c(p, bt);
+        cplx ebn = fn * (elt - p->e_ref);
         if (p->quad == OFK_QUAD_RIGHT)
-            w = w - p->dt * (elt - p->e_ref);
+            w = w - p->dt * ebn;
         else
-            w = w - (0.5 * p->dt) * ((el - p->e_ref) + (elt - p->e_ref));
+            w = w - (0.5 * p->dt) * (eb + ebn);
         for (int j = 0; j < 6; ++j) {
             y[j] = yt[j];
             b[j] = bt[j];
         }
         el = elt;
+        f = fn;
+        eb = ebn;
         if (sample_every > 0 && (k + 1) % sample_every == 0) dell[s++] = cimag(w) / h;
     }
     return 0;

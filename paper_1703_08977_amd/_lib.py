@@ -39,7 +39,7 @@ class HeFkParams(ctypes.Structure):
         ("precision", ctypes.c_int32), ("n_metropolis", ctypes.c_int32),
         ("Z", ctypes.c_double), ("theta", ctypes.c_double * 4), ("dt", ctypes.c_double),
         ("e_ref", ctypes.c_double), ("metropolis_sigma", ctypes.c_double), ("init_sigma", ctypes.c_double),
-        ("seed", ctypes.c_uint64), ("walker_offset", ctypes.c_uint64), ("n_walkers", ctypes.c_int64),
+        ("drift_limit", ctypes.c_double), ("seed", ctypes.c_uint64), ("walker_offset", ctypes.c_uint64), ("n_walkers", ctypes.c_int64),
     ]
 
 

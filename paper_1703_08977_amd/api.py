@@ -38,6 +38,7 @@ def make_params(cfg: dict, n_walkers: int | None = None, walker_offset: int = 0,
     p.e_ref = float(c.get("e_ref", 0.0))
     p.metropolis_sigma = float(c.get("metropolis_sigma", 0.5))
     p.init_sigma = float(c.get("init_sigma", 1.0))
+    p.drift_limit = float(c.get("drift_limit", 0.0))
     p.seed = int(c.get("seed", 0)) & ((1 << 64) - 1)
     p.walker_offset = int(walker_offset)
     p.n_walkers = int(n_walkers if n_walkers is not None else c["n_walkers"])

@@ -451,8 +451,9 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
 template <typename R>
 struct WalkerState {
     R y[6];
-    R b[6];
-    R el;
+    R b[6];     // drift used by the next step (limited when drift_limit > 0)
+    R el;       // local energy at y
+    double eb;  // integrand V_P = E_L - e_ref at y (limited when drift_limit > 0)
     int sign;
     double lnw;
 };
@@ -460,12 +461,33 @@ struct WalkerState {
 struct StepConst {
     double dt, half_dt, e_ref;
     int quad_right;
+    double limit_adt;  // drift_limit * dt (0: no limiting)
 };
 
+// Drift / integrand limiting near singular points: f = 2 / (1 + sqrt(1 + 2 a dt |b|^2)),
+// b -> f b, E_L - e_ref -> f (E_L - e_ref).
+template <typename R>
+HD double limit_drift(const StepConst& sc, R b[6], R el)
+{
+    double e = (double)el - sc.e_ref;
+    if (sc.limit_adt > 0.0) {
+        R v2 = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v2 += b[k] * b[k];
+        const R x2 = (R)(2.0 * sc.limit_adt) * v2;
+        const R f = (R)2 / ((R)1 + m::sqrt_((R)1 + x2));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b[k] *= f;
+        e *= (double)f;
+    }
+    return e;
+}
+
 template <typename R, int TRIAL>
-HD void walker_reset(const TrialParams<R>& tp, WalkerState<R>& w)
+HD void walker_reset(const TrialParams<R>& tp, const StepConst& sc, WalkerState<R>& w)
 {
     w.sign = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el);
+    w.eb = limit_drift<R>(sc, w.b, w.el);
 }
 
 // Y' = Y + dt b + sqrt(dt) xi; node crossing absorbs (lnw = -inf, frozen);
@@ -483,12 +505,12 @@ HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, R dt_r, R sqd
         w.lnw = -INFINITY;
         return;
     }
-    const double en = (double)elt - sc.e_ref;
+    const double en = limit_drift<R>(sc, bt, elt);
     double lw;
     if (sc.quad_right)
         lw = w.lnw - sc.dt * en;
     else
-        lw = w.lnw - sc.half_dt * (((double)w.el - sc.e_ref) + en);
+        lw = w.lnw - sc.half_dt * (w.eb + en);
     if (!__builtin_isfinite((double)elt)) lw = NAN;
     w.lnw = lw;
 #pragma unroll
@@ -497,6 +519,7 @@ HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, R dt_r, R sqd
         w.b[k] = bt[k];
     }
     w.el = elt;
+    w.eb = en;
     w.sign = st;
 }
 

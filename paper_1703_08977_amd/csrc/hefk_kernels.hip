@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void propagate_kernel(const KArgs a)
 #pragma unroll
         for (int k = 0; k < 6; ++k) w.y[k] = x[(int64_t)k * n + ii];
         w.lnw = a.lnw[ii];
-        walker_reset<R, TRIAL>(tp, w);
+        walker_reset<R, TRIAL>(tp, a.sc, w);
 
         sample_row<R>(a, part, first, valid, w, red);
         if (a.ckpt && valid) {
@@ -246,7 +246,8 @@ int check_params(const he_fk_params* p)
     if (p->precision != HE_FK_FP64 && p->precision != HE_FK_MIXED) return HE_FK_EINVAL;
     if (p->n_metropolis < 0) return HE_FK_EINVAL;
     if (!finite_pos(p->Z) || !finite_pos(p->dt) || !finite_pos(p->metropolis_sigma) ||
-        !finite_pos(p->init_sigma) || !std::isfinite(p->e_ref))
+        !finite_pos(p->init_sigma) || !std::isfinite(p->e_ref) || !(p->drift_limit >= 0.0) ||
+        !std::isfinite(p->drift_limit))
         return HE_FK_EINVAL;
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(p->theta[k])) return HE_FK_EINVAL;
@@ -279,6 +280,7 @@ static KArgs make_args(const he_fk_params* p)
     a.sc.half_dt = 0.5 * p->dt;
     a.sc.e_ref = p->e_ref;
     a.sc.quad_right = (p->quad == HE_FK_QUAD_RIGHT);
+    a.sc.limit_adt = p->drift_limit * p->dt;
     a.dt = p->dt;
     a.sqdt = std::sqrt(p->dt);
     a.dtf = (float)p->dt;

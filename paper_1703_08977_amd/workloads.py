@@ -16,6 +16,8 @@ Keys:
                32-bit uniforms) or 2 (one block per step, 21-bit uniforms)
   precision    "fp64" | "mixed" (FP32 coordinates, drift and E_L; FP64 ln w)
   n_metropolis, metropolis_sigma, init_sigma  (start ensemble ~ |psi|^2)
+  drift_limit  a >= 0: drift / integrand limiting near the singular points of
+               an inexact trial function (0: the plain discretisation)
 
 The e_ref values are variational energies of each trial function measured
 with 2^16 Metropolis samples; any value works.
@@ -62,7 +64,7 @@ HE_PZ_16M = dict(
     name="he_2P_pz_16m", trial="pz", sym=1, theta=[2.0, 0.3, 0.5, 0.5], Z=2.0, ee=1,
     n_walkers=1 << 24, dt=0.0005, n_steps=12000, sample_every=100, seed=0, e_ref=-2.1194,
     noise="gauss", quad="trapezoid", contract=1, precision="mixed",
-    n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0, seeds=list(range(16)))
+    n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0, drift_limit=1.0, seeds=list(range(16)))
 
 WORKLOADS = {w["name"]: w for w in
              (HE_GROUND_EXPO_4K, HE_GROUND_PADE_1M, HE_TRIPLET_4M, HE_GRAD_PADE_256K, HE_PZ_16M)}

@@ -3,7 +3,7 @@
 // same sampling as the propagate kernel, one walker at a time.
 //
 // stdin, line 1: trial sym ee noise contract quad precision n_met Z t0 t1 t2 t3
-//                dt e_ref metropolis_sigma init_sigma seed n_steps sample_every
+//                dt e_ref metropolis_sigma init_sigma drift_limit seed n_steps sample_every
 // line 2:        n id_0 ... id_{n-1}
 // stdout, per walker one line: x0[6] x[6] lnw el ell[ns] els[ns]
 #include <cstdio>
@@ -16,7 +16,7 @@ using namespace hefk;
 
 struct Cfg {
     int trial, sym, ee, noise, contract, quad, precision, n_met;
-    double Z, th[4], dt, e_ref, msig, isig;
+    double Z, th[4], dt, e_ref, msig, isig, limit;
     unsigned long long seed;
     long n_steps, sample_every;
 };
@@ -50,12 +50,13 @@ void run_walker(const Cfg& c, unsigned long long g)
     WalkerState<R> w;
     for (int k = 0; k < 6; ++k) w.y[k] = (R)y0[k];
     w.lnw = 0.0;
-    walker_reset<R, TRIAL>(tp, w);
     StepConst sc;
     sc.dt = c.dt;
     sc.half_dt = 0.5 * c.dt;
     sc.e_ref = c.e_ref;
     sc.quad_right = c.quad == 1;
+    sc.limit_adt = c.limit * c.dt;
+    walker_reset<R, TRIAL>(tp, sc, w);
     const R dt_r = (R)c.dt, sqdt_r = (R)std::sqrt(c.dt);
     std::vector<double> ell, els;
     ell.push_back(w.lnw);
@@ -101,10 +102,10 @@ void dispatch(const Cfg& c, unsigned long long g)
 int main()
 {
     Cfg c;
-    if (std::scanf("%d %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %ld %ld", &c.trial, &c.sym,
+    if (std::scanf("%d %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %ld %ld", &c.trial, &c.sym,
                    &c.ee, &c.noise, &c.contract, &c.quad, &c.precision, &c.n_met, &c.Z, &c.th[0], &c.th[1],
-                   &c.th[2], &c.th[3], &c.dt, &c.e_ref, &c.msig, &c.isig, &c.seed, &c.n_steps,
-                   &c.sample_every) != 20)
+                   &c.th[2], &c.th[3], &c.dt, &c.e_ref, &c.msig, &c.isig, &c.limit, &c.seed, &c.n_steps,
+                   &c.sample_every) != 21)
         return 2;
     long n = 0;
     if (std::scanf("%ld", &n) != 1) return 2;

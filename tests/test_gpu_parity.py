@@ -56,6 +56,7 @@ CASES = [
     ("he_2P_pz_16m", dict(dt=0.002, precision="fp64")),
     ("he_2P_pz_16m", dict(dt=0.002, precision="fp64", sym=-1, theta=[2.0, 0.3, 0.25, 0.5], contract=2)),
     ("hydrogen", dict()),
+    ("he_1s_pade_1m", dict(dt=0.01, drift_limit=0.5, contract=2)),
 ]
 
 
