@@ -25,7 +25,10 @@ from __future__ import annotations
 
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 39.32e12
 
-PHILOX_BLOCK = 10 * (2 + 4)  # 10 rounds x (two 32x32->64 multiplies, four xors); key schedule on the scalar unit
+# Philox4x32-10 block per step: 10 rounds x (two 32x32->64 multiplies, four xors), less the
+# work that depends only on the walker id, the phase and the key (round 1 and the first
+# multiply of round 2, computed once per walker); the key schedule runs on the scalar unit.
+PHILOX_BLOCK = 9 * (2 + 4) - 1
 
 F32 = {"sqrt": 1, "rcp": 1, "exp": 2, "expm1": 10, "log": 2, "sincos": 2}
 F64 = {"sqrt": 8, "rcp": 10, "exp": 20, "expm1": 25, "log": 25, "sincos": 35}
