@@ -195,24 +195,32 @@ size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_steps, int32_t 
                                 int32_t ckpt_every);
 
 /*
- * he_fk_grad: d/d(theta0, theta1) of J = sum_s gL[s] L_s (L_s the log space
- * average of sample row s of a he_fk_propagate call from step 0), for the
- * nodeless trials (EXPO, PADE) in FP64, at fixed start positions and fixed
- * noise (pathwise / fixed-noise derivative of the discrete map), by a reverse
- * sweep over checkpoint segments with the noise regenerated from Philox.
- *   y0      : walker state at step 0 (x read; lnw, el ignored);
- *   ckpt    : device, the checkpoints of that propagate call;
- *   samples : device, its sample rows (m and S0 give the walker weights);
+ * he_fk_grad: d/d(theta0, theta1) = d/d(alpha, beta) of J = sum_s gL[s] L_s,
+ * L_s the log space average of sample row s of one he_fk_propagate call from
+ * step 0 with checkpoints, for the nodeless trials (EXPO, PADE), FP64, no
+ * drift limiting.  The derivative is pathwise: start positions (checkpoint
+ * row 0) and noise are held fixed, so it is the exact derivative of the
+ * discrete map the propagate call computed.  Reverse sweep over the checkpoint
+ * segments; each segment is recomputed from its checkpoint into the scratch
+ * tape with the noise regenerated from Philox, then one reverse-mode pass
+ * through the trial evaluation per step gives grad_Y and d_theta of
+ * dt lambda . b + A_j (E_L - e_ref) (lambda the adjoint of the position,
+ * A_j the weight of step j's local energy in J).
+ *   ckpt    : device, the checkpoints [n_steps/ckpt_every + 1][7][N] of that call;
+ *   samples : device, its sample rows (m and S0 give each walker's share of L_s);
  *   gL      : HOST, [n_steps / sample_every + 1];
- *   flags   : 0 or HE_FK_GRAD_SCORE;
- *   dtheta  : device, [2] binary64 output.
- * Constraints: as he_fk_propagate with ckpt != NULL; ckpt_every % sample_every == 0
- * or sample_every % ckpt_every == 0.
- * Errors: EINVAL (also for node trials or MIXED precision), ESCRATCH, EDEVICE.
+ *   flags   : 0 or HE_FK_GRAD_SCORE (adds sum_s gL[s] sum_i (p_is - 1/N) 2 d ln|psi(Y0_i)|/d theta,
+ *             the derivative through the |psi|^2 law of the start positions);
+ *   scratch : device, at least he_fk_grad_scratch_bytes(...) bytes;
+ *   dtheta  : device, [2] binary64 output (written by the last kernel of the call).
+ * Constraints: n_steps % sample_every == 0, n_steps % ckpt_every == 0, and one of
+ * ckpt_every, sample_every divides the other; p, seed, walker_offset and n_walkers
+ * as in the propagate call.
+ * Errors: EINVAL (also node trials, MIXED precision, drift_limit != 0), ESCRATCH, EDEVICE.
  */
-int he_fk_grad(const he_fk_params* p, const he_fk_walkers* y0, const double* ckpt, const double* samples,
-               const double* gL, int64_t n_steps, int32_t sample_every, int32_t ckpt_every, int32_t flags,
-               void* scratch, size_t scratch_bytes, double* dtheta, void* stream);
+int he_fk_grad(const he_fk_params* p, const double* ckpt, const double* samples, const double* gL,
+               int64_t n_steps, int32_t sample_every, int32_t ckpt_every, int32_t flags, void* scratch,
+               size_t scratch_bytes, double* dtheta, void* stream);
 
 /* Static description of an error code. */
 const char* he_fk_strerror(int code);

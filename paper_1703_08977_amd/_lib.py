@@ -77,7 +77,7 @@ def lib():
         L.he_fk_energy.restype = ctypes.c_int
         L.he_fk_grad_scratch_bytes.argtypes = [pp, i64, i32, i32]
         L.he_fk_grad_scratch_bytes.restype = ctypes.c_size_t
-        L.he_fk_grad.argtypes = [pp, wp, vp, vp, dp, i64, i32, i32, i32, vp, ctypes.c_size_t, vp, vp]
+        L.he_fk_grad.argtypes = [pp, vp, vp, dp, i64, i32, i32, i32, vp, ctypes.c_size_t, vp, vp]
         L.he_fk_grad.restype = ctypes.c_int
         L.he_fk_strerror.argtypes = [ctypes.c_int]
         L.he_fk_strerror.restype = ctypes.c_char_p

@@ -93,10 +93,10 @@ def he_fk_grad_scratch_bytes(p, n_steps, sample_every, ckpt_every) -> int:
     return int(lib().he_fk_grad_scratch_bytes(ctypes.byref(p), int(n_steps), int(sample_every), int(ckpt_every)))
 
 
-def he_fk_grad(p, y0, ckpt, samples, gL, n_steps, sample_every, ckpt_every, flags, scratch, scratch_bytes, dtheta,
+def he_fk_grad(p, ckpt, samples, gL, n_steps, sample_every, ckpt_every, flags, scratch, scratch_bytes, dtheta,
                stream=None) -> int:
     g = np.ascontiguousarray(gL, dtype=np.float64)
-    rc = lib().he_fk_grad(ctypes.byref(p), ctypes.byref(y0), ctypes.c_void_p(ckpt), ctypes.c_void_p(samples),
+    rc = lib().he_fk_grad(ctypes.byref(p), ctypes.c_void_p(ckpt), ctypes.c_void_p(samples),
                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_steps), int(sample_every),
                           int(ckpt_every), int(flags), ctypes.c_void_p(scratch), ctypes.c_size_t(scratch_bytes),
                           ctypes.c_void_p(dtheta), _stream(stream))

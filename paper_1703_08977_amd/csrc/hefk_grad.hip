@@ -1,25 +1,256 @@
-// hefk_grad.hip -- pathwise (fixed-noise) gradient of the log space average
-// with respect to the trial parameters: reverse sweep over checkpoint segments.
+// hefk_grad.hip -- pathwise (fixed start, fixed noise) gradient of
+// J = sum_s gL_s L_s with respect to the trial parameters (alpha, beta):
+// one thread per walker walks the checkpoint segments backwards, recomputes
+// each segment from its checkpoint into a scratch tape (noise regenerated
+// from Philox), and runs the adjoint recursion of hefk_adjoint.hpp over it.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <cmath>
 
 #include "he_fk.h"
+#include "hefk_adjoint.hpp"
+#include "hefk_reduce.hpp"
+#include "hefk_sweep.hpp"
+
+namespace hefk {
+
+int check_params(const he_fk_params* p);  // hefk_kernels.hip
+
+namespace {
+
+constexpr int kGradBlock = 256;
+
+struct GArgs {
+    TrialParams<double> tp;
+    StepConst sc;
+    double dt, sqdt;
+    uint32_t key0, key1;
+    uint64_t walker_offset;
+    int64_t n;
+    int32_t n_steps, sample_every, ckpt_every, score;
+    const double* ckpt;     // [n_ckpt][7][n]
+    const double* samples;  // [n_samples][8]
+    const double* g;        // [n_samples]
+    double* tape;           // [ckpt_every + 1][7][n]
+    double* partial;        // [gridDim.x][2]
+    double inv_n_total, g_sum;
+};
+
+// Tape in device memory, structure of arrays over walkers (coalesced).
+struct DeviceTape {
+    const double* ckpt;
+    double* tape;
+    int64_t n, i;
+    __device__ void load_ckpt(int c, double y[6], double& lnw) const
+    {
+        const double* b = ckpt + (size_t)c * 7 * n;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
+        lnw = b[6 * n + i];
+    }
+    __device__ void put(int slot, const double y[6], double lnw)
+    {
+        double* b = tape + (size_t)slot * 7 * n;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b[(int64_t)k * n + i] = y[k];
+        b[6 * n + i] = lnw;
+    }
+    __device__ void get(int slot, double y[6], double& lnw) const
+    {
+        const double* b = tape + (size_t)slot * 7 * n;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
+        lnw = b[6 * n + i];
+    }
+};
+
+struct SampleView {
+    const double* rows;
+    const double* g;
+    __device__ double m(int s) const { return rows[8 * s]; }
+    __device__ double s0(int s) const { return rows[8 * s + 1]; }
+    __device__ double gs(int s) const { return g[s]; }
+};
+
+template <int TRIAL, int NOISE>
+__global__ __launch_bounds__(kGradBlock) void grad_kernel(const GArgs a)
+{
+    __shared__ double red[8];
+    const int64_t i = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;
+    double gth[2] = {0.0, 0.0};
+    if (i < a.n) {
+        const uint64_t gid = a.walker_offset + (uint64_t)i;
+        Stream st;
+        st.k0 = a.key0;
+        st.k1 = a.key1;
+        st.g0 = (uint32_t)gid;
+        st.g1 = (uint32_t)(gid >> 32);
+        DeviceTape tape{a.ckpt, a.tape, a.n, i};
+        SampleView sv{a.samples, a.g};
+        double P = 0.0;
+        walker_reverse<TRIAL, NOISE>(a.tp, a.sc, a.dt, a.sqdt, st, a.n_steps, a.sample_every, a.ckpt_every, sv,
+                                     tape, gth, &P);
+        if (a.score) {
+            double y0[6], l0, sc[2];
+            tape.load_ckpt(0, y0, l0);
+            dlnpsi_dtheta<TRIAL>(a.tp, y0, sc);
+            const double wgt = P - a.g_sum * a.inv_n_total;
+            gth[0] += 2.0 * sc[0] * wgt;
+            gth[1] += 2.0 * sc[1] * wgt;
+        }
+    }
+    // deterministic block sum of the two components
+    const double s0 = wave_sum(gth[0]);
+    const double s1 = wave_sum(gth[1]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * wave] = s0;
+        red[2 * wave + 1] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.partial[2 * blockIdx.x] = (red[0] + red[2]) + (red[4] + red[6]);
+        a.partial[2 * blockIdx.x + 1] = (red[1] + red[3]) + (red[5] + red[7]);
+    }
+}
+
+// Sum of the per-block partials in a fixed order (one block).
+__global__ __launch_bounds__(kGradBlock) void grad_sum_kernel(const double* __restrict__ partial, int n_parts,
+                                                              double* __restrict__ out)
+{
+    __shared__ double sh[2 * kGradBlock];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < n_parts; b += kGradBlock) {
+        s0 += partial[2 * b];
+        s1 += partial[2 * b + 1];
+    }
+    sh[2 * threadIdx.x] = s0;
+    sh[2 * threadIdx.x + 1] = s1;
+    __syncthreads();
+    for (int w = kGradBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sh[2 * threadIdx.x] += sh[2 * (threadIdx.x + w)];
+            sh[2 * threadIdx.x + 1] += sh[2 * (threadIdx.x + w) + 1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0];
+        out[1] = sh[1];
+    }
+}
+
+typedef void (*GradFn)(GArgs);
+
+GradFn pick(int trial, int noise)
+{
+    if (trial == TRIAL_EXPO) {
+        if (noise == NOISE_G1) return grad_kernel<TRIAL_EXPO, NOISE_G1>;
+        if (noise == NOISE_G2) return grad_kernel<TRIAL_EXPO, NOISE_G2>;
+        return grad_kernel<TRIAL_EXPO, NOISE_PM1>;
+    }
+    if (noise == NOISE_G1) return grad_kernel<TRIAL_PADE, NOISE_G1>;
+    if (noise == NOISE_G2) return grad_kernel<TRIAL_PADE, NOISE_G2>;
+    return grad_kernel<TRIAL_PADE, NOISE_PM1>;
+}
+
+struct Layout {
+    size_t tape, partial, g, total;
+    int64_t blocks;
+};
+
+int layout(const he_fk_params* p, int64_t n_steps, int32_t sample_every, int32_t ckpt_every, Layout* L)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->trial != HE_FK_TRIAL_EXPO && p->trial != HE_FK_TRIAL_PADE) return HE_FK_EINVAL;
+    if (p->precision != HE_FK_FP64 || p->drift_limit != 0.0) return HE_FK_EINVAL;
+    if (n_steps < 1 || sample_every < 1 || ckpt_every < 1) return HE_FK_EINVAL;
+    if (n_steps % sample_every || n_steps % ckpt_every) return HE_FK_EINVAL;
+    if (ckpt_every % sample_every && sample_every % ckpt_every) return HE_FK_EINVAL;
+    if (n_steps >= (int64_t(1) << 31)) return HE_FK_EINVAL;
+    const int64_t n = p->n_walkers;
+    L->blocks = (n + kGradBlock - 1) / kGradBlock;
+    if (L->blocks > INT32_MAX) return HE_FK_EINVAL;
+    auto up256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    L->tape = 0;
+    L->partial = up256((size_t)(ckpt_every + 1) * 7 * (size_t)n * sizeof(double));
+    L->g = L->partial + up256((size_t)L->blocks * 2 * sizeof(double));
+    L->total = L->g + up256((size_t)(n_steps / sample_every + 1) * sizeof(double));
+    return HE_FK_OK;
+}
+
+}  // namespace
+}  // namespace hefk
+
+using namespace hefk;
 
 extern "C" size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_steps, int32_t sample_every,
                                            int32_t ckpt_every)
 {
-    (void)p;
-    (void)n_steps;
-    (void)sample_every;
-    (void)ckpt_every;
-    return 0;
+    Layout L;
+    if (layout(p, n_steps, sample_every, ckpt_every, &L)) return 0;
+    return L.total;
 }
 
-extern "C" int he_fk_grad(const he_fk_params* p, const he_fk_walkers* y0, const double* ckpt,
-                          const double* samples, const double* gL, int64_t n_steps, int32_t sample_every,
-                          int32_t ckpt_every, int32_t flags, void* scratch, size_t scratch_bytes,
-                          double* dtheta, void* stream)
+extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const double* samples, const double* gL,
+                          int64_t n_steps, int32_t sample_every, int32_t ckpt_every, int32_t flags, void* scratch,
+                          size_t scratch_bytes, double* dtheta, void* stream)
 {
-    (void)p; (void)y0; (void)ckpt; (void)samples; (void)gL; (void)n_steps; (void)sample_every;
-    (void)ckpt_every; (void)flags; (void)scratch; (void)scratch_bytes; (void)dtheta; (void)stream;
-    return HE_FK_EINVAL;
+    Layout L;
+    int rc = layout(p, n_steps, sample_every, ckpt_every, &L);
+    if (rc) return rc;
+    if (!ckpt || !samples || !gL || !scratch || !dtheta) return HE_FK_EINVAL;
+    if (flags & ~HE_FK_GRAD_SCORE) return HE_FK_EINVAL;
+    if (scratch_bytes < L.total) return HE_FK_ESCRATCH;
+    const int64_t n_samples = n_steps / sample_every + 1;
+    double g_sum = 0.0;
+    for (int64_t s = 0; s < n_samples; ++s) {
+        if (!std::isfinite(gL[s])) return HE_FK_EINVAL;
+        g_sum += gL[s];
+    }
+    char* base = (char*)scratch;
+    GArgs a;
+    memset(&a, 0, sizeof(a));
+    a.tp.A = p->theta[0];
+    a.tp.beta = p->theta[1];
+    a.tp.c = p->theta[2];
+    a.tp.a = p->theta[3];
+    a.tp.Z = p->Z;
+    a.tp.ee = (double)p->ee;
+    a.tp.sym = 1.0;
+    a.sc.dt = p->dt;
+    a.sc.half_dt = 0.5 * p->dt;
+    a.sc.e_ref = p->e_ref;
+    a.sc.quad_right = (p->quad == HE_FK_QUAD_RIGHT);
+    a.sc.limit_adt = 0.0;
+    a.dt = p->dt;
+    a.sqdt = std::sqrt(p->dt);
+    a.key0 = (uint32_t)p->seed;
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.walker_offset = p->walker_offset;
+    a.n = p->n_walkers;
+    a.n_steps = (int32_t)n_steps;
+    a.sample_every = sample_every;
+    a.ckpt_every = ckpt_every;
+    a.score = (flags & HE_FK_GRAD_SCORE) ? 1 : 0;
+    a.ckpt = ckpt;
+    a.samples = samples;
+    a.tape = (double*)(base + L.tape);
+    a.partial = (double*)(base + L.partial);
+    a.g = (double*)(base + L.g);
+    a.g_sum = g_sum;
+    // 1/N of the space average: every walker of the propagate call counts (n_total of row 0)
+    a.inv_n_total = 1.0 / (double)p->n_walkers;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync((void*)a.g, gL, (size_t)n_samples * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return HE_FK_EDEVICE;
+    const int nk = p->noise == HE_FK_NOISE_PM1 ? NOISE_PM1 : (p->contract == 2 ? NOISE_G2 : NOISE_G1);
+    hipLaunchKernelGGL(pick(p->trial, nk), dim3((unsigned)L.blocks), dim3(kGradBlock), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return HE_FK_EDEVICE;
+    hipLaunchKernelGGL(grad_sum_kernel, dim3(1), dim3(kGradBlock), 0, s, (const double*)a.partial, (int)L.blocks,
+                       dtheta);
+    return hipGetLastError() == hipSuccess ? HE_FK_OK : HE_FK_EDEVICE;
 }

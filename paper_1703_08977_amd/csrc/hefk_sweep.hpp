@@ -1,0 +1,59 @@
+// hefk_sweep.hpp -- the per-walker reverse sweep of the pathwise gradient
+// (host + device).  The tape accessor holds the checkpoints (state every
+// ckpt_every steps) and a scratch tape for one segment; the sample view gives
+// m_s, S0_s of each sample row and the objective weights g_s.
+#pragma once
+
+#include "hefk_adjoint.hpp"
+
+namespace hefk {
+
+template <int TRIAL, int NOISE, class Samples, class Tape>
+HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, double dt, double sqdt, const Stream& st,
+                       int n_steps, int sample_every, int ckpt_every, const Samples& sv, Tape& tape, double gth[2],
+                       double* p_total)
+{
+    const bool right = sc.quad_right != 0;
+    const int n_seg = n_steps / ckpt_every;
+    double lam[6] = {0, 0, 0, 0, 0, 0};
+    double P = 0.0;
+    for (int seg = n_seg - 1; seg >= 0; --seg) {
+        const int k0 = seg * ckpt_every;
+        // recompute the segment from its checkpoint (same arithmetic as the forward kernel)
+        WalkerState<double> w;
+        tape.load_ckpt(seg, w.y, w.lnw);
+        walker_reset<double, TRIAL>(tp, sc, w);
+        tape.put(0, w.y, w.lnw);
+        NoiseGen<double, NOISE> noise;
+        for (int k = 0; k < ckpt_every; ++k) {
+            double xi[6];
+            noise.draw(st, (uint32_t)(k0 + k), xi);
+            walker_step<double, TRIAL>(tp, sc, dt, sqdt, xi, w);
+            tape.put(k + 1, w.y, w.lnw);
+        }
+        // reverse over the steps of the segment (step k0 belongs to the segment below, except k0 = 0)
+        const int j_lo = (seg == 0) ? 0 : k0 + 1;
+        for (int j = k0 + ckpt_every; j >= j_lo; --j) {
+            double y[6], lnw;
+            tape.get(j - k0, y, lnw);
+            double H = 0.0;
+            if (j % sample_every == 0) {
+                const int s = j / sample_every;
+                H = sv.gs(s) * ::exp(lnw - sv.m(s)) / sv.s0(s);
+            }
+            const double A = adjoint_weight(j, P, H, dt, right);
+            double V[6], gy[6], gt[2];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) V[k] = dt * lam[k];
+            vjp_trial<TRIAL>(tp, y, V, A, gy, gt);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) lam[k] += gy[k];
+            gth[0] += gt[0];
+            gth[1] += gt[1];
+            P += H;
+        }
+    }
+    *p_total = P;
+}
+
+}  // namespace hefk

@@ -1,0 +1,111 @@
+// Host build of the gradient's per-walker reverse sweep (hefk_sweep.hpp) for
+// CPU checks against the oracle's complex-step derivative.
+//
+// stdin line 1: trial ee quad contract n_met Z t0 t1 t2 t3 dt e_ref metropolis_sigma init_sigma seed
+//               n_steps sample_every ckpt_every
+// line 2: n_samples, then n_samples triples (m_s S0_s g_s)
+// line 3: n id_0 ... id_{n-1}
+// stdout per walker: dJ/dalpha dJ/dbeta P (P = sum_s g_s p_{i,s})
+#include <cstdio>
+#include <vector>
+
+#include "hefk_sweep.hpp"
+
+using namespace hefk;
+
+struct HostTape {
+    std::vector<double> ck, tp;  // [n_ckpt][7], [ckpt_every + 1][7]
+    void load_ckpt(int c, double y[6], double& lnw) const
+    {
+        for (int k = 0; k < 6; ++k) y[k] = ck[7 * c + k];
+        lnw = ck[7 * c + 6];
+    }
+    void put(int s, const double y[6], double lnw)
+    {
+        for (int k = 0; k < 6; ++k) tp[7 * s + k] = y[k];
+        tp[7 * s + 6] = lnw;
+    }
+    void get(int s, double y[6], double& lnw) const
+    {
+        for (int k = 0; k < 6; ++k) y[k] = tp[7 * s + k];
+        lnw = tp[7 * s + 6];
+    }
+};
+
+struct HostSamples {
+    std::vector<double> m_, s0_, g_;
+    double m(int s) const { return m_[s]; }
+    double s0(int s) const { return s0_[s]; }
+    double gs(int s) const { return g_[s]; }
+};
+
+template <int TRIAL, int NOISE>
+void one(const TrialParams<double>& tp, const StepConst& sc, int n_met, double msig, double isig,
+         unsigned long long seed, unsigned long long g, int n_steps, int se, int ce, const HostSamples& hs)
+{
+    Stream st;
+    st.k0 = (uint32_t)seed;
+    st.k1 = (uint32_t)(seed >> 32);
+    st.g0 = (uint32_t)g;
+    st.g1 = (uint32_t)(g >> 32);
+    WalkerState<double> w;
+    init_walker<TRIAL>(tp, st, n_met, isig, msig, w.y);
+    w.lnw = 0.0;
+    walker_reset<double, TRIAL>(tp, sc, w);
+    HostTape tape;
+    tape.ck.assign(7 * (n_steps / ce + 1), 0.0);
+    tape.tp.assign(7 * (ce + 1), 0.0);
+    auto save = [&](int c) {
+        for (int k = 0; k < 6; ++k) tape.ck[7 * c + k] = w.y[k];
+        tape.ck[7 * c + 6] = w.lnw;
+    };
+    save(0);
+    NoiseGen<double, NOISE> noise;
+    const double dt = sc.dt, sq = std::sqrt(sc.dt);
+    for (int k = 0; k < n_steps; ++k) {
+        double xi[6];
+        noise.draw(st, (uint32_t)k, xi);
+        walker_step<double, TRIAL>(tp, sc, dt, sq, xi, w);
+        if ((k + 1) % ce == 0) save((k + 1) / ce);
+    }
+    double gth[2] = {0, 0}, P = 0;
+    walker_reverse<TRIAL, NOISE>(tp, sc, dt, sq, st, n_steps, se, ce, hs, tape, gth, &P);
+    std::printf("%.17g %.17g %.17g\n", gth[0], gth[1], P);
+}
+
+int main()
+{
+    int trial, ee, quad, contract, n_met, n_steps, se, ce;
+    double Z, th[4], dt, e_ref, msig, isig;
+    unsigned long long seed;
+    if (std::scanf("%d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %d %d %d", &trial, &ee, &quad, &contract,
+                   &n_met, &Z, &th[0], &th[1], &th[2], &th[3], &dt, &e_ref, &msig, &isig, &seed, &n_steps, &se,
+                   &ce) != 18)
+        return 2;
+    int ns;
+    if (std::scanf("%d", &ns) != 1) return 2;
+    HostSamples hs;
+    for (int s = 0; s < ns; ++s) {
+        double a, b, c;
+        if (std::scanf("%lf %lf %lf", &a, &b, &c) != 3) return 2;
+        hs.m_.push_back(a);
+        hs.s0_.push_back(b);
+        hs.g_.push_back(c);
+    }
+    TrialParams<double> tp{th[0], th[1], th[2], th[3], Z, (double)ee, 1.0};
+    StepConst sc{dt, 0.5 * dt, e_ref, quad, 0.0};
+    long n;
+    if (std::scanf("%ld", &n) != 1) return 2;
+    for (long i = 0; i < n; ++i) {
+        unsigned long long g;
+        if (std::scanf("%llu", &g) != 1) return 2;
+        if (trial == TRIAL_EXPO) {
+            if (contract == 2) one<TRIAL_EXPO, NOISE_G2>(tp, sc, n_met, msig, isig, seed, g, n_steps, se, ce, hs);
+            else one<TRIAL_EXPO, NOISE_G1>(tp, sc, n_met, msig, isig, seed, g, n_steps, se, ce, hs);
+        } else {
+            if (contract == 2) one<TRIAL_PADE, NOISE_G2>(tp, sc, n_met, msig, isig, seed, g, n_steps, se, ce, hs);
+            else one<TRIAL_PADE, NOISE_G1>(tp, sc, n_met, msig, isig, seed, g, n_steps, se, ce, hs);
+        }
+    }
+    return 0;
+}

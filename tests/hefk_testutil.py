@@ -90,3 +90,38 @@ def host_run(cfg, ids, n_steps, sample_every, precision=0):
     arr = np.array([[float(v) for v in ln.split()] for ln in out.strip().split("\n")])
     return {"x0": arr[:, :6], "x": arr[:, 6:12], "lnw": arr[:, 12], "el": arr[:, 13],
             "ell": arr[:, 14:14 + ns], "els": arr[:, 14 + ns:]}
+
+
+_ADJ = None
+
+
+def adjoint_harness():
+    """Build (once) the host build of the gradient's per-walker reverse sweep."""
+    global _ADJ
+    if _ADJ is None:
+        import shutil
+        import tempfile
+        hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+        exe = os.path.join(tempfile.mkdtemp(prefix="hefk_adj_"), "adjoint_host_check")
+        subprocess.check_call([hipcc, "-O2", "-std=c++17", "--offload-arch=gfx950", "-I", CSRC, "-I",
+                               os.path.join(ROOT, "include"), "-o", exe,
+                               os.path.join(ROOT, "tests", "adjoint_host_check.cpp")],
+                              stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+        _ADJ = exe
+    return _ADJ
+
+
+def adjoint_host_run(cfg, ids, n_steps, sample_every, ckpt_every, samples, g):
+    """Per-walker (dJ/dalpha, dJ/dbeta, P) from the host build of the reverse sweep."""
+    import oracle
+    th = [float(v) for v in (list(cfg["theta"]) + [0.0] * 4)[:4]]
+    line = "%d %d %d %d %d %r %r %r %r %r %r %r %r %r %d %d %d %d" % (
+        oracle.TRIALS[cfg["trial"]], cfg["ee"], 1 if cfg.get("quad") == "right" else 0, cfg.get("contract", 1),
+        cfg["n_metropolis"], float(cfg["Z"]), *th, float(cfg["dt"]), float(cfg["e_ref"]),
+        float(cfg["metropolis_sigma"]), float(cfg["init_sigma"]), int(cfg["seed"]), n_steps, sample_every,
+        ckpt_every)
+    l2 = "%d " % len(samples) + " ".join("%r %r %r" % (float(samples[s, 0]), float(samples[s, 1]), float(g[s]))
+                                         for s in range(len(samples)))
+    inp = line + "\n" + l2 + "\n%d %s\n" % (len(ids), " ".join(str(int(i)) for i in ids))
+    out = subprocess.run([adjoint_harness()], input=inp, capture_output=True, text=True, check=True).stdout
+    return np.array([[float(v) for v in ln.split()] for ln in out.strip().split("\n")])

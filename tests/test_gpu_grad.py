@@ -1,0 +1,132 @@
+"""GPU tests of the pathwise gradient he_fk_grad (through the C ABI):
+against the oracle's complex-step derivative (same start, same noise),
+against central differences of the GPU forward map with common random
+numbers at the full 2^18-walker size, the start-law score term, the
+autograd wrapper, and the argument checks."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_08977_amd import workloads as W
+
+from hefk_testutil import gpu_available, log_mean_weight
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an AMD Instinct GPU")]
+
+
+def _forward(cfg, n=None, x0=None):
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    e = Ensemble(cfg, n_walkers=n)
+    if x0 is None:
+        e.init()
+    else:
+        e.x.copy_(x0)
+        e.lnw.zero_()
+    x_start = e.x.clone()
+    ns, se, ce = cfg["n_steps"], cfg["sample_every"], cfg["ckpt_every"]
+    ckpt = torch.empty((ns // ce + 1, 7, e.n), dtype=torch.float64, device="cuda")
+    s = e.propagate(0, ns, se, ckpt=ckpt, ckpt_every=ce)
+    torch.cuda.synchronize()
+    return e, ckpt, s, x_start
+
+
+def _grad(e, ckpt, s, cfg, gL, flags=0):
+    import torch
+    from paper_1703_08977_amd import api
+    ns, se, ce = cfg["n_steps"], cfg["sample_every"], cfg["ckpt_every"]
+    nb = api.he_fk_grad_scratch_bytes(e.p, ns, se, ce)
+    scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    d = torch.empty(2, dtype=torch.float64, device="cuda")
+    api.he_fk_grad(e.p, ckpt.data_ptr(), s.data_ptr(), gL, ns, se, ce, flags, scratch.data_ptr(), nb, d.data_ptr())
+    return d.cpu().numpy()
+
+
+@pytest.mark.parametrize("over,ce", [({}, 50), ({"quad": "right"}, 25), ({"contract": 2}, 100),
+                                     ({"noise": "pm1"}, 50), ({"trial": "expo", "theta": [1.8]}, 50)])
+def test_grad_matches_oracle_complex_step(over, ce):
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, ckpt_every=ce, **over)
+    n = 3001
+    e, ckpt, s, x0 = _forward(cfg, n)
+    gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
+    got = _grad(e, ckpt, s, cfg, gL)
+    y0 = x0.t().contiguous().cpu().numpy()
+    ref = oracle.grad_objective(cfg, np.arange(n), y0, 200, 50, gL)
+    assert np.abs(got - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-3), (got, ref)
+
+
+def test_grad_score_term_matches_oracle():
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, ckpt_every=50)
+    n = 2048
+    e, ckpt, s, x0 = _forward(cfg, n)
+    gL = np.array([0.2, 0.0, 0.5, -1.0, 1.3])
+    from paper_1703_08977_amd import _lib
+    got = _grad(e, ckpt, s, cfg, gL, flags=_lib.GRAD_SCORE)
+    ref = oracle.grad_objective(cfg, np.arange(n), x0.t().contiguous().cpu().numpy(), 200, 50, gL, score=True)
+    assert np.abs(got - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-3), (got, ref)
+
+
+def test_grad_full_size_against_central_differences():
+    # 2^18 walkers x 1000 steps, checkpoints every 50: d E(T=2) / d(alpha, beta) against
+    # central differences of the GPU forward map at the same start positions and noise.
+    cfg = W.get("he_1s_pade_grad_256k")
+    e, ckpt, s, x0 = _forward(cfg)
+    dts = cfg["dt"] * cfg["sample_every"]
+    ns = cfg["n_steps"] // cfg["sample_every"] + 1
+    gL = np.zeros(ns)
+    gL[-1], gL[-2] = -1.0 / dts, 1.0 / dts  # E(T) = e_ref - (L[-1] - L[-2]) / dts
+    got = _grad(e, ckpt, s, cfg, gL)
+    fd = []
+    for d in range(2):
+        vals = []
+        for sgn in (+1, -1):
+            th = list(cfg["theta"])
+            th[d] += sgn * 1e-5
+            c = dict(cfg, theta=th)
+            _, _, sp, _ = _forward(c, x0=x0)
+            vals.append(float(np.sum(gL * log_mean_weight(sp.cpu().numpy()))))
+        fd.append((vals[0] - vals[1]) / 2e-5)
+    fd = np.array(fd)
+    assert np.abs(got - fd).max() <= 1e-6 * max(np.abs(fd).max(), 1e-3), (got, fd)
+
+
+def test_autograd_function_uses_the_adjoint():
+    import torch
+    from paper_1703_08977_amd.autograd import energy_fd, log_space_average
+    cfg = W.get("he_1s_pade_grad_256k", n_walkers=4096, n_steps=200, sample_every=50, ckpt_every=50)
+    theta = torch.tensor([2.0, 0.25], dtype=torch.float64, requires_grad=True)
+    L = log_space_average(theta, cfg)
+    E = energy_fd(L, cfg)
+    E.backward()
+    e, ckpt, s, x0 = _forward(cfg)
+    gL = np.zeros(5)
+    dts = cfg["dt"] * cfg["sample_every"]
+    gL[-1], gL[-2] = -1.0 / dts, 1.0 / dts
+    ref = _grad(e, ckpt, s, cfg, gL)
+    assert np.allclose(theta.grad.numpy(), ref, rtol=1e-12, atol=0)
+    assert abs(float(E) - (cfg["e_ref"] - (log_mean_weight(s.cpu().numpy())[-1] -
+                                           log_mean_weight(s.cpu().numpy())[-2]) / dts)) < 1e-12
+
+
+def test_grad_rejects_unsupported_cases():
+    import torch
+    from paper_1703_08977_amd import _lib, api
+    cfg = W.get("he_1s_pade_grad_256k", n_walkers=512, n_steps=100, sample_every=50, ckpt_every=50)
+    e, ckpt, s, _ = _forward(cfg)
+    gL = np.zeros(3)
+    for over in ({"trial": "pz", "sym": 1, "theta": [2, 0.3, 0.5, 0.5]}, {"precision": "mixed"},
+                 {"drift_limit": 1.0}):
+        p = api.make_params(dict(cfg, **over))
+        assert api.he_fk_grad_scratch_bytes(p, 100, 50, 50) == 0
+    nb = api.he_fk_grad_scratch_bytes(e.p, 100, 50, 50)
+    scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    d = torch.empty(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.HeFkError) as ei:
+        api.he_fk_grad(e.p, ckpt.data_ptr(), s.data_ptr(), gL, 100, 50, 50, 0, scratch.data_ptr(), nb - 1,
+                       d.data_ptr())
+    assert ei.value.code == _lib.HE_FK_ESCRATCH
+    with pytest.raises(_lib.HeFkError) as ei:
+        api.he_fk_grad(e.p, ckpt.data_ptr(), s.data_ptr(), gL, 100, 50, 30, 0, scratch.data_ptr(), nb,
+                       d.data_ptr())
+    assert ei.value.code == _lib.HE_FK_EINVAL

@@ -15,7 +15,7 @@ from oracle import estimators as est
 from paper_1703_08977_amd import _lib, api
 from paper_1703_08977_amd import workloads as W
 
-from hefk_testutil import ROOT, host_run
+from hefk_testutil import ROOT, adjoint_host_run, host_run
 
 
 def test_library_exports_every_declared_symbol():
@@ -181,3 +181,24 @@ def test_kernel_arithmetic_host_build_matches_oracle(name, over):
     assert np.abs(h["ell"][f] - r["ell"][f]).max() < 1e-12
     alive = np.isfinite(r["lnw"])
     assert np.abs(h["x"][alive] - r["x"][alive]).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Host build of the gradient's reverse sweep against the oracle's
+# complex-step derivative (two independent methods for the same quantity).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("over,ckpt_every", [({}, 50), ({}, 25), ({"quad": "right"}, 50),
+                                             ({"trial": "expo", "theta": [1.8]}, 50), ({"contract": 2}, 100)])
+def test_reverse_sweep_host_build_matches_complex_step(over, ckpt_every):
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, **over)
+    ids = np.arange(192) * 31 + 5
+    r = oracle.run(cfg, ids, 200, 50)
+    gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
+    a = adjoint_host_run(cfg, ids, 200, 50, ckpt_every, r["samples"], gL)
+    got = a[:, :2].sum(axis=0)
+    ref = oracle.grad_objective(cfg, ids, r["x0"], 200, 50, gL)
+    for d in range(2):
+        assert abs(got[d] - ref[d]) <= 1e-11 * max(abs(ref[d]), 1e-3)
+    # P = sum_s g_s p_is sums to sum_s g_s over walkers
+    assert abs(a[:, 2].sum() - gL.sum()) < 1e-12
