@@ -81,8 +81,8 @@ extern "C" {
  *               f_5 = (w2 >> 21) | ((w3 >> 21) & 1023) << 11; uniforms (f + 1/2) 2^-21,
  *               identical in both precisions.
  *   +-1 walk:   step k reads block k / 20, word (k mod 20) / 5, bits 6 (k mod 5) + j.
- * The start ensemble always uses contract 1 in binary64 (both precisions start
- * from the same walkers).
+ * The start ensemble is drawn in binary64 for both precisions (see he_fk_init),
+ * so a MIXED and an FP64 run of the same seed start from the same walkers.
  */
 
 typedef struct {
@@ -127,10 +127,14 @@ typedef struct {
 /*
  * he_fk_init: the start ensemble Y0 ~ psi_T^2 (the start point of eq. (4) is
  * left open by the paper; a |psi_T|^2 start makes L(0) = 0 and E_mixed(0)
- * the variational energy).  Per walker: Y = init_sigma * xi(phase 0,
- * vector 0); then n_metropolis steps Y' = Y + metropolis_sigma * xi(phase 1,
- * vector m), accepted iff ln u < 2 (ln|psi(Y')| - ln|psi(Y)|), u the uniform
- * of word 2 of block 2m+1.  Writes x, el = E_L(Y0), lnw = 0.
+ * the variational energy).  Per walker, in binary64 for both precisions:
+ * Y = init_sigma * xi(phase 0, Gaussian vector 0, contract 1); then
+ * n_metropolis steps with a uniform box proposal of standard deviation
+ * metropolis_sigma: Philox block m of phase 1 gives six 16-bit fields f_j
+ * (low/high halves of words 0, 1, 2), Y'_j = Y_j + sqrt(3) metropolis_sigma
+ * (2 (f_j + 1/2) 2^-16 - 1), accepted iff ln u < 2 (ln|psi(Y')| - ln|psi(Y)|)
+ * with u = (w3 + 1/2) 2^-32.  Writes x (rounded to binary32 for MIXED),
+ * el = E_L(Y0), lnw = 0.
  * Errors: EINVAL (bad params / NULL pointers), EDEVICE.
  */
 int he_fk_init(const he_fk_params* p, const he_fk_walkers* w, void* stream);

@@ -317,19 +317,30 @@ static double trial_lnpsi(const ofk_params* p, const double y[6])
 /* Initial ensemble: Y0 ~ |psi|^2 by Metropolis, per walker.                 */
 /* ------------------------------------------------------------------------ */
 
-/* Walker g: Y = init_sigma * xi(phase 0, vector 0); then n_metropolis steps of
-   Y' = Y + sigma_M xi(phase 1, vector m), accepted iff ln u < 2 (ln|psi(Y')| - ln|psi(Y)|),
-   with u the spare uniform of the same vector. */
+/* Walker g: Y = init_sigma * xi(phase 0, vector 0) (Gaussian, contract 1); then
+   n_metropolis steps with a uniform box proposal, symmetric about Y:
+   block m of phase 1 gives six 16-bit fields f_j (low and high halves of words
+   0, 1, 2) and the accept uniform u = (w3 + 1/2) 2^-32;
+   Y'_j = Y_j + h (2 (f_j + 1/2) 2^-16 - 1), h = sqrt(3) metropolis_sigma (the
+   box of standard deviation metropolis_sigma); accepted iff
+   ln u < 2 (ln|psi(Y')| - ln|psi(Y)|). */
 void ofk_init_walker(const ofk_params* p, uint64_t g, double y[6])
 {
-    double xi[6], u;
+    double xi[6];
     ofk_gauss6_c1(p, OFK_PHASE_INIT, 0u, g, xi, NULL);
     for (int j = 0; j < 6; ++j) y[j] = p->init_sigma * xi[j];
     double lp = trial_lnpsi(p, y);
+    const double h = sqrt(3.0) * p->metropolis_sigma;
     for (int m = 0; m < p->n_metropolis; ++m) {
+        uint32_t w[4];
+        block_words(p, OFK_PHASE_METROPOLIS, (uint32_t)m, g, w);
         double yt[6];
-        ofk_gauss6_c1(p, OFK_PHASE_METROPOLIS, (uint32_t)m, g, xi, &u);
-        for (int j = 0; j < 6; ++j) yt[j] = y[j] + p->metropolis_sigma * xi[j];
+        for (int j = 0; j < 6; ++j) {
+            uint32_t f = (w[j / 2] >> (16 * (j % 2))) & 0xFFFFu;
+            double v = ((double)f + 0.5) * 0x1p-16;
+            yt[j] = y[j] + h * (2.0 * v - 1.0);
+        }
+        double u = ofk_u32_to_unit(w[3]);
         double lpt = trial_lnpsi(p, yt);
         if (log(u) < 2.0 * (lpt - lp)) {
             memcpy(y, yt, sizeof(double) * 6);

@@ -12,7 +12,8 @@ import os
 import torch  # noqa: F401  (load torch's HIP runtime before libhefk)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhefk.so")
+# HEFK_LIBRARY may point at another in-tree build of the same sources (e.g. other launch bounds)
+LIB_PATH = os.environ.get("HEFK_LIBRARY") or os.path.join(_HERE, "libhefk.so")
 
 HE_FK_OK = 0
 HE_FK_EINVAL = -1

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-LIB = os.path.join(PKG, "libhefk.so")
+LIB = os.environ.get("HEFK_LIBRARY") or os.path.join(PKG, "libhefk.so")
 SOURCES = ["hefk_kernels.hip", "hefk_grad.hip", "hefk_energy.cpp"]
 ARCH = os.environ.get("HEFK_OFFLOAD_ARCH", "gfx950")
 
@@ -26,12 +26,12 @@ def flags():
             "-ffp-contract=on",
             # packed FP32 arithmetic stays off (v_pk_* forms are avoided on this target)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include"), "-I", HERE]
+            "-I", os.path.join(ROOT, "include"), "-I", HERE] + os.environ.get("HEFK_DEFINES", "").split()
 
 
 def build(verbose: bool = False) -> str:
     """Compile every source to an object, then link the shared library."""
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build" + os.environ.get("HEFK_BUILD_TAG", ""))
     os.makedirs(bdir, exist_ok=True)
     objs = []
     for src in SOURCES:

@@ -37,6 +37,7 @@ HD double rcp_(double x) { return 1.0 / x; }
 HD double exp_(double x) { return ::exp(x); }
 HD double expm1_(double x) { return ::expm1(x); }
 HD double log_(double x) { return ::log(x); }
+HD double neg2log_(double x) { return -2.0 * ::log(x); }
 // sin(2 pi u), cos(2 pi u) for u in (0, 1)
 HD void sincos2pi(double u, double* s, double* c)
 {
@@ -82,6 +83,15 @@ HD float log_(float x)
     return ::logf(x);
 #endif
 }
+// -2 ln x = (-2 ln 2) log2 x: one v_log_f32 and one multiply
+HD float neg2log_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x) * -1.3862943611198906f;
+#else
+    return -2.0f * ::logf(x);
+#endif
+}
 HD void sincos2pi(float u, float* s, float* c)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -104,14 +114,24 @@ struct Words {
     uint32_t w[4];
 };
 
+// three-input xor: one v_bitop3_b32 (truth table 0x96) on gfx950
+HD uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 HD Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -133,9 +153,21 @@ struct Stream {
     HD Words block(uint32_t phase, uint32_t b) const { return philox(b, phase, g0, g1, k0, k1); }
 };
 
-// uniform (0,1) from a 32-bit word: binary64 (w + 1/2) 2^-32; binary32 from the top 23 bits
+// uniform (0,1) from a 32-bit word: binary64 (w + 1/2) 2^-32; binary32 from the top 23
+// bits, ((w >> 9) + 1/2) 2^-23, built as the float 1.m with m = w >> 9 (one funnel shift
+// of 0x7F:w by 9) minus (1 - 2^-24), exact in binary32
 HD double unit32(uint32_t w, double) { return ((double)w + 0.5) * 0x1p-32; }
-HD float unit32(uint32_t w, float) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+HD float unit32(uint32_t w, float)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t bits = __builtin_amdgcn_alignbit(0x7Fu, w, 9u);
+#else
+    const uint32_t bits = 0x3F800000u | (w >> 9);
+#endif
+    float f;
+    __builtin_memcpy(&f, &bits, 4);
+    return f - 0.99999994039535522461f;  // 1 - 2^-24
+}
 // uniform (0,1) from a 21-bit field, exact in both precisions
 template <typename R>
 HD R unit21(uint32_t f)
@@ -146,7 +178,7 @@ HD R unit21(uint32_t f)
 template <typename R>
 HD void box_muller(R u1, R u2, R* a, R* b)
 {
-    const R rad = m::sqrt_((R)-2.0 * m::log_(u1));
+    const R rad = m::sqrt_(m::neg2log_(u1));
     R s, c;
     m::sincos2pi(u2, &s, &c);
     *a = rad * c;
@@ -277,36 +309,16 @@ HD Jas<R> jastrow(const TrialParams<R>& p, const Geo<R>& g)
     return j;
 }
 
-// Swap electrons 1 and 2 in place (the TRIPLET and PZ evaluations are written
-// for (A - a)(r1 - r2) <= 0 so that no exponential can overflow; the other
-// half-space follows from the exchange symmetry psi(2,1) = -psi(1,2) (TRIPLET)
-// or sym * psi(1,2) (PZ)).
-template <typename R>
-HD void swap_electrons(R y[6])
-{
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const R t = y[k];
-        y[k] = y[3 + k];
-        y[3 + k] = t;
-    }
-}
-
 // Drift b = grad ln|psi|, local energy E_L = -(1/2) Lap(psi)/psi + V and the sign
 // of psi (0 on the node).  V = -Z/r1 - Z/r2 + ee/r12.
+//
+// TRIPLET and PZ combine f = e^{-A r1 - a r2} and g = e^{-A r2 - a r1}; with
+// d = (A - a)(r1 - r2), g / f = e^d.  Both are evaluated as Phi / max(f, g):
+// (t1, t2) = (1, e^d) for d <= 0 and (e^{-d}, 1) for d > 0, so no exponential can
+// overflow and every ratio grad Phi / Phi, Lap Phi / Phi is unchanged.
 template <typename R, int TRIAL>
-HD int trial_eval(const TrialParams<R>& p, const R y_in[6], R b[6], R& el)
+HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el)
 {
-    R y[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) y[k] = y_in[k];
-    bool swapped = false;
-    if (has_node<TRIAL>::value) {
-        const R s1 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
-        const R s2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
-        swapped = (p.A - p.a) * (s1 - s2) > (R)0;
-        if (swapped) swap_electrons(y);
-    }
     Geo<R> g;
     geometry(y, g);
     int sign = 1;
@@ -329,17 +341,22 @@ HD int trial_eval(const TrialParams<R>& p, const R y_in[6], R b[6], R& el)
         }
         el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + p.A * j.up * w - j.upp - j.up * j.up + j.ee_term;
     } else if (TRIAL == TRIAL_TRIPLET) {
-        // Phi = e^{-A r1 - a r2} D, D = 1 - e^d = -expm1(d), d = (A - a)(r1 - r2) <= 0
+        // Phi / max(f, g) = t1 - t2 = D; with q = t2 / t1 this is the (r1 < r2) form
+        //   g1 = (-A t1 + a t2) / D, g2 = (-a t1 + A t2) / D,
+        //   Lap_1 Phi / Phi = [t1 (A^2 - 2A/r1) - t2 (a^2 - 2a/r1)] / D (and 1 <-> 2 roles for Lap_2)
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
-        const R em = m::expm1_(d);
-        const R D = -em;
-        const R q = (R)1 + em;
+        const bool lo = d <= (R)0;
+        const R em = m::expm1_(lo ? d : -d);  // e^{-|d|} - 1, accurate near the node
+        const R e = (R)1 + em;
+        const R t1 = lo ? (R)1 : e;
+        const R t2 = lo ? e : (R)1;
+        const R D = lo ? -em : em;  // t1 - t2 without cancellation
         const R iD = m::rcp_(D);
-        const R g1 = (-p.A + p.a * q) * iD;
-        const R g2 = (-p.a + p.A * q) * iD;
-        const R l1 = ((p.A * p.A - (R)2 * p.A * g.i1) - q * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
-        const R l2 = ((p.a * p.a - (R)2 * p.a * g.i2) - q * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
+        const R g1 = (-p.A * t1 + p.a * t2) * iD;
+        const R g2 = (-p.a * t1 + p.A * t2) * iD;
+        const R l1 = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) - t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
+        const R l2 = (t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
         R c1 = 0, c2 = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -350,27 +367,29 @@ HD int trial_eval(const TrialParams<R>& p, const R y_in[6], R b[6], R& el)
         }
         el = (R)-0.5 * (l1 + l2) - j.up * (g1 * c1 - g2 * c2) - j.upp - j.up * j.up + j.ee_term -
              p.Z * (g.i1 + g.i2);
-        sign = (D > (R)0) ? 1 : 0;
-        if (swapped) sign = -sign;
-    } else {  // TRIAL_PZ: Phi = e^{-A r1 - a r2} P, P = z2 + sym z1 rho, rho = e^{(A - a)(r1 - r2)} <= 1
+        sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
+    } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
-        const R rho = m::exp_((p.A - p.a) * (g.r1 - g.r2));
+        const R d = (p.A - p.a) * (g.r1 - g.r2);
+        const bool lo = d <= (R)0;
+        const R e = m::exp_(lo ? d : -d);
+        const R t1 = lo ? (R)1 : e;
+        const R t2 = (lo ? e : (R)1) * p.sym;
         const R z1 = y[2], z2 = y[5];
-        const R sr = p.sym * rho;
-        const R P = z2 + sr * z1;
+        const R P = z2 * t1 + t2 * z1;
         const R iP = m::rcp_(P);
-        const R k1 = p.A * z2 + sr * p.a * z1;  // grad_1 Phi/f = -k1 h1 + sr zhat
-        const R k2 = p.a * z2 + sr * p.A * z1;  // grad_2 Phi/f = zhat - k2 h2
+        const R k1 = p.A * z2 * t1 + t2 * p.a * z1;  // grad_1 Phi / max = -k1 h1 + t2 zhat
+        const R k2 = p.a * z2 * t1 + t2 * p.A * z1;  // grad_2 Phi / max = t1 zhat - k2 h2
         R gp1[3], gp2[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             gp1[k] = -k1 * g.h1[k] * iP;
             gp2[k] = -k2 * g.h2[k] * iP;
         }
-        gp1[2] += sr * iP;
-        gp2[2] += iP;
-        const R l1 = (z2 * (p.A * p.A - (R)2 * p.A * g.i1) + sr * z1 * (p.a * p.a - (R)4 * p.a * g.i1)) * iP;
-        const R l2 = (z2 * (p.a * p.a - (R)4 * p.a * g.i2) + sr * z1 * (p.A * p.A - (R)2 * p.A * g.i2)) * iP;
+        gp1[2] += t2 * iP;
+        gp2[2] += t1 * iP;
+        const R l1 = (z2 * t1 * (p.A * p.A - (R)2 * p.A * g.i1) + t2 * z1 * (p.a * p.a - (R)4 * p.a * g.i1)) * iP;
+        const R l2 = (z2 * t1 * (p.a * p.a - (R)4 * p.a * g.i2) + t2 * z1 * (p.A * p.A - (R)2 * p.A * g.i2)) * iP;
         R cr = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -380,48 +399,37 @@ HD int trial_eval(const TrialParams<R>& p, const R y_in[6], R b[6], R& el)
         }
         el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         sign = (P > (R)0) ? 1 : ((P < (R)0) ? -1 : 0);
-        if (swapped && p.sym < (R)0) sign = -sign;
-    }
-    if (swapped) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const R t = b[k];
-            b[k] = b[3 + k];
-            b[3 + k] = t;
-        }
     }
     return sign;
 }
 
 // ln|psi| (binary64; -inf on the node), for the Metropolis start.
 template <int TRIAL>
-HD double trial_lnpsi(const TrialParams<double>& p, const double y_in[6])
+HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
 {
-    double y[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) y[k] = y_in[k];
-    if (has_node<TRIAL>::value) {
-        const double s1 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
-        const double s2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
-        if ((p.A - p.a) * (s1 - s2) > 0.0) swap_electrons(y);
-    }
     const double r1 = ::sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     const double r2 = ::sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
     const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
     const double r12 = ::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
     const double U = (TRIAL == TRIAL_EXPO) ? 0.0 : p.c * r12 / (1.0 + p.beta * r12);
     if (TRIAL == TRIAL_EXPO || TRIAL == TRIAL_PADE) return -p.A * (r1 + r2) + U;
+    // ln max(f, g) + ln|Phi / max(f, g)|
+    const double d = (p.A - p.a) * (r1 - r2);
+    const bool lo = d <= 0.0;
+    const double lnmax = lo ? (-p.A * r1 - p.a * r2) : (-p.A * r2 - p.a * r1);
     if (TRIAL == TRIAL_TRIPLET) {
-        const double D = -::expm1((p.A - p.a) * (r1 - r2));
-        return -p.A * r1 - p.a * r2 + ::log(::fabs(D)) + U;
+        const double em = ::expm1(lo ? d : -d);
+        return lnmax + ::log(::fabs(em)) + U;
     }
-    const double rho = ::exp((p.A - p.a) * (r1 - r2));
-    const double P = y[5] + p.sym * y[2] * rho;
-    return -p.A * r1 - p.a * r2 + ::log(::fabs(P)) + U;
+    const double e = ::exp(lo ? d : -d);
+    const double P = y[5] * (lo ? 1.0 : e) + p.sym * y[2] * (lo ? e : 1.0);
+    return lnmax + ::log(::fabs(P)) + U;
 }
 
-// Start position of one walker: Y = init_sigma xi(phase 0, vector 0), then
-// n_met Metropolis steps on |psi|^2 with proposal width sigma_m (binary64).
+// Start position of one walker (binary64): Y = init_sigma xi(phase 0, vector 0),
+// then n_met Metropolis steps on |psi|^2 with a uniform box proposal of standard
+// deviation sigma_m: Philox block m of phase 1 gives six 16-bit displacement fields
+// (halves of words 0..2) and the accept word 3.
 template <int TRIAL>
 HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, double init_sigma,
                     double sigma_m, double y[6])
@@ -431,11 +439,16 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
 #pragma unroll
     for (int k = 0; k < 6; ++k) y[k] = init_sigma * xi[k];
     double lp = trial_lnpsi<TRIAL>(tp, y);
+    const double h = 1.7320508075688772 * sigma_m;  // sqrt(3) sigma: the box of standard deviation sigma
     for (int mstep = 0; mstep < n_met; ++mstep) {
-        double u, yt[6];
-        gauss6_c1<double>(st, PHASE_METROPOLIS, (uint32_t)mstep, xi, &u);
+        const Words w = st.block(PHASE_METROPOLIS, (uint32_t)mstep);
+        double yt[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) yt[k] = y[k] + sigma_m * xi[k];
+        for (int k = 0; k < 6; ++k) {
+            const uint32_t f = (w.w[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
+            yt[k] = y[k] + h * (2.0 * (((double)f + 0.5) * 0x1p-16) - 1.0);
+        }
+        const double u = unit32(w.w[3], 0.0);
         const double lpt = trial_lnpsi<TRIAL>(tp, yt);
         if (::log(u) < 2.0 * (lpt - lp)) {
 #pragma unroll

@@ -15,6 +15,16 @@ namespace hefk {
 
 constexpr int kBlock = 256;  // 4 waves of 64 lanes; one walker per lane
 
+// Minimum resident waves per SIMD the propagate kernels are compiled for
+// (register budget 512 / waves).  The binary32 step keeps its loop free of
+// spills at a smaller budget than the binary64 one.
+#ifndef HEFK_WAVES_F32
+#define HEFK_WAVES_F32 6
+#endif
+#ifndef HEFK_WAVES_F64
+#define HEFK_WAVES_F64 1
+#endif
+
 struct KArgs {
     TrialParams<double> tpd;
     TrialParams<float> tpf;
@@ -100,7 +110,8 @@ __device__ __forceinline__ void sample_row(const KArgs& a, double* part_row, boo
 }
 
 template <typename R, int TRIAL, int NOISE>
-__global__ __launch_bounds__(kBlock) void propagate_kernel(const KArgs a)
+__global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVES_F64) void propagate_kernel(
+    const KArgs a)
 {
     __shared__ double red[kRedSlots];
     const TrialParams<R>& tp = tparams<R>(a);

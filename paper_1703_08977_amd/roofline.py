@@ -30,18 +30,20 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 39.32e12
 # multiply of round 2, computed once per walker); the key schedule runs on the scalar unit.
 PHILOX_BLOCK = 9 * (2 + 4) - 1
 
+# "log" is -2 ln x (the Box-Muller radius argument) including its constant factor
 F32 = {"sqrt": 1, "rcp": 1, "exp": 2, "expm1": 10, "log": 2, "sincos": 2}
-F64 = {"sqrt": 8, "rcp": 10, "exp": 20, "expm1": 25, "log": 25, "sincos": 35}
+F64 = {"sqrt": 8, "rcp": 10, "exp": 20, "expm1": 25, "log": 26, "sincos": 35}
 
 
 def noise_slots(precision: str, noise: str, contract: int) -> float:
     f = F32 if precision == "mixed" else F64
     if noise == "pm1":
         return PHILOX_BLOCK / 20.0 + 6 * 2  # one block per 20 steps; bit extract + select per coordinate
-    box_muller = 3 * (f["log"] + 1 + f["sqrt"] + f["sincos"] + 2)
+    box_muller = 3 * (f["log"] + f["sqrt"] + f["sincos"] + 2)
     if contract == 2:
         return PHILOX_BLOCK + 14 + 6 * 2 + box_muller  # 21-bit field extraction, convert + scale
-    return 2 * PHILOX_BLOCK + 6 * 3 + box_muller  # shift, convert, scale per uniform
+    per_uniform = 2 if precision == "mixed" else 2  # funnel shift + add (binary32); convert + scale (binary64)
+    return 2 * PHILOX_BLOCK + 6 * per_uniform + box_muller
 
 
 def trial_slots(precision: str, trial: str) -> float:

@@ -13,7 +13,9 @@ Keys:
   noise        "gauss" (Euler-Maruyama) | "pm1" (the paper's +/-1 walk)
   quad         "trapezoid" | "right" (the paper's right end-point Riemann sum)
   contract     Gaussian stream contract: 1 (two Philox blocks per step,
-               32-bit uniforms) or 2 (one block per step, 21-bit uniforms)
+               32-bit uniforms) or 2 (one block per step, 21-bit uniforms,
+               the same in both precisions: the mixed-vs-FP64 workloads use it
+               so that both precisions draw identical increments)
   precision    "fp64" | "mixed" (FP32 coordinates, drift and E_L; FP64 ln w)
   n_metropolis, metropolis_sigma, init_sigma  (start ensemble ~ |psi|^2)
   drift_limit  a >= 0: drift / integrand limiting near the singular points of
@@ -47,7 +49,7 @@ HE_GROUND_PADE_1M = dict(
 HE_TRIPLET_4M = dict(
     name="he_2tripS_4m", trial="triplet", theta=[2.0, 0.3, 0.25, 0.6], Z=2.0, ee=1,
     n_walkers=1 << 22, dt=0.001, n_steps=4000, sample_every=50, seed=0, e_ref=-2.1222,
-    noise="gauss", quad="trapezoid", contract=1, precision="mixed",
+    noise="gauss", quad="trapezoid", contract=2, precision="mixed",
     n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0)
 
 # Gradient of E(T = 2) with respect to (alpha, beta) of the Pade-Jastrow trial:
@@ -63,7 +65,7 @@ HE_GRAD_PADE_256K = dict(
 HE_PZ_16M = dict(
     name="he_2P_pz_16m", trial="pz", sym=1, theta=[2.0, 0.3, 0.5, 0.5], Z=2.0, ee=1,
     n_walkers=1 << 24, dt=0.0005, n_steps=12000, sample_every=100, seed=0, e_ref=-2.1194,
-    noise="gauss", quad="trapezoid", contract=1, precision="mixed",
+    noise="gauss", quad="trapezoid", contract=2, precision="mixed",
     n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0, drift_limit=1.0, seeds=list(range(16)))
 
 WORKLOADS = {w["name"]: w for w in
