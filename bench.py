@@ -127,7 +127,8 @@ def main():
         sys.exit(2)
     import torch
     from paper_1703_08977_amd import workloads as W
-    from paper_1703_08977_amd.roofline import PEAK_SLOTS_PER_S, fp32_flops_per_walker_step, slots_per_walker_step
+    from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, fp32_flops_per_walker_step, slots_per_walker_step,
+                                               transcendentals_per_walker_step)
 
     over = {}
     if args.precision:
@@ -150,7 +151,7 @@ def main():
     peak = PEAK_SLOTS_PER_S / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
             "traffic": None, "kernel": "propagate_kernel", "slots_per_walker_step": slots,
-            "kernel_ms": kern * 1e3}
+            "transcendentals_per_walker_step": transcendentals_per_walker_step(cfg), "kernel_ms": kern * 1e3}
     fl = fp32_flops_per_walker_step(cfg)
     if fl:
         roof["fp32_tflops"] = fl * n * K / kern / 1e12

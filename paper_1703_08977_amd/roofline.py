@@ -4,74 +4,118 @@ The step is per-walker scalar arithmetic (transcendental, integer and
 floating point; no contraction, no HBM traffic between sampling times), so
 its roofline is the vector-ALU issue rate.
 
-Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s,
-one operation per lane per clock (a wave64 instruction occupies a 16-lane
-SIMD for 4 clocks).  This is the published 78.6 TFLOP/s binary32 (and
-binary64) FMA rate divided by 2 flops; the 157.3 TFLOP/s binary32 figure
-needs packed (v_pk_*) instructions, which this build does not use.
+Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s
+on the main VALU pipe, one operation per lane per clock (a wave64
+instruction occupies a 16-lane SIMD for 4 clocks).  This is the published
+78.6 TFLOP/s binary32 (and binary64) FMA rate divided by 2 flops; the 157.3
+TFLOP/s binary32 figure needs packed (v_pk_*) instructions, which this build
+does not use.
 
-Work: every elementary operation of the step's formulas counts one issue
-slot -- add, mul, fma, compare, select, convert, 32-bit integer op, 32x32->64
-multiply, and each binary32 hardware transcendental (v_sqrt, v_rcp, v_exp,
-v_log, v_sin, v_cos).  On gfx950 these all issue at the full rate: the
-compiled binary32 step of the P_z trial has 318 VALU instructions and runs at
-1024 x 2.4e9 x 16 / 318 = 1.24e11 walker-steps/s, the measured rate.  Binary64
-library functions count their polynomial evaluation and range reduction:
-sqrt 8, division 10, exp 20, expm1 25, log 25, sincospi 35.
-Counts are per term of the formulas (they are not read back from the
-compiled code); the tables below list them.
+Work: every elementary operation of the step's formulas counts one slot of
+the main pipe -- add, mul, fma, compare, select, convert, 32-bit integer op,
+32x32->64 multiply, three-input xor.  The binary32 hardware transcendentals
+(v_sqrt, v_rcp, v_exp, v_log, v_sin, v_cos) are counted apart: on gfx950 they
+issue beside the main pipe (the counters of the mixed P_z step show 0.272
+wave-instructions per SIMD-cycle against 0.25 for the main pipe alone, which
+is its instruction count with the transcendentals left out).  Binary64
+library functions count their polynomial and range-reduction operations on
+the main pipe: sqrt 8, division 10, exp 20, expm1 25, -2 log 26, sincospi 35.
+Counts follow the formulas term by term (they are not read back from the
+compiled code).
 """
 from __future__ import annotations
 
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 39.32e12
 
-# Philox4x32-10 block per step: 10 rounds x (two 32x32->64 multiplies, four xors), less the
-# work that depends only on the walker id, the phase and the key (round 1 and the first
-# multiply of round 2, computed once per walker); the key schedule runs on the scalar unit.
-PHILOX_BLOCK = 9 * (2 + 4) - 1
+# Philox4x32-10 block per step: 10 rounds x (two 32x32->64 multiplies, two three-input
+# xors), less the work that depends only on the walker id, the phase and the key (round 1
+# and the first multiply of round 2, computed once per walker); the key schedule runs on
+# the scalar unit.
+PHILOX_BLOCK = 9 * (2 + 2) - 1
 
-# "log" is -2 ln x (the Box-Muller radius argument) including its constant factor
-F32 = {"sqrt": 1, "rcp": 1, "exp": 2, "expm1": 10, "log": 2, "sincos": 2}
-F64 = {"sqrt": 8, "rcp": 10, "exp": 20, "expm1": 25, "log": 26, "sincos": 35}
+# (main-pipe operations, transcendental instructions) per function
+F32 = {"sqrt": (0, 1), "rcp": (0, 1), "exp": (1, 1), "expm1": (9, 1), "log": (1, 1), "sincos": (0, 2)}
+F64 = {"sqrt": (8, 0), "rcp": (10, 0), "exp": (20, 0), "expm1": (25, 0), "log": (26, 0), "sincos": (35, 0)}
 
 
-def noise_slots(precision: str, noise: str, contract: int) -> float:
-    f = F32 if precision == "mixed" else F64
+class _Count:
+    def __init__(self):
+        self.main = 0.0
+        self.trans = 0.0
+
+    def ops(self, n):
+        self.main += n
+
+    def fn(self, table, name, times=1):
+        m, t = table[name]
+        self.main += m * times
+        self.trans += t * times
+
+
+def _noise(c: _Count, f, noise: str, contract: int):
     if noise == "pm1":
-        return PHILOX_BLOCK / 20.0 + 6 * 2  # one block per 20 steps; bit extract + select per coordinate
-    box_muller = 3 * (f["log"] + f["sqrt"] + f["sincos"] + 2)
+        c.ops(PHILOX_BLOCK / 20.0 + 6 * 2)  # one block per 20 steps; bit extract + select per coordinate
+        return
+    # Box-Muller per pair: -2 log u1, sqrt, sin and cos of 2 pi u2, two products
+    for _ in range(3):
+        c.fn(f, "log")
+        c.fn(f, "sqrt")
+        c.fn(f, "sincos")
+        c.ops(2)
     if contract == 2:
-        return PHILOX_BLOCK + 14 + 6 * 2 + box_muller  # 21-bit field extraction, convert + scale
-    per_uniform = 2 if precision == "mixed" else 2  # funnel shift + add (binary32); convert + scale (binary64)
-    return 2 * PHILOX_BLOCK + 6 * per_uniform + box_muller
+        c.ops(PHILOX_BLOCK + 14 + 6 * 2)  # one block, 21-bit field extraction, convert + scale
+    else:
+        c.ops(2 * PHILOX_BLOCK + 6 * 2)  # two blocks; funnel shift + add (binary32), convert + scale (binary64)
 
 
-def trial_slots(precision: str, trial: str) -> float:
-    f = F32 if precision == "mixed" else F64
-    geometry = 3 + 3 * (3 + f["sqrt"]) + 3 * f["rcp"] + 9  # differences, norms, inverses, unit vectors
-    jastrow = 1 + f["rcp"] + 1 + 1 + 2 + 4
-    swap = 9 + 12  # half-space test, electrons in, drift out
+def _trial(c: _Count, f, trial: str):
+    # geometry: differences, three squared norms, sqrt, reciprocal, unit vectors
+    c.ops(3 + 3 * 3 + 9)
+    c.fn(f, "sqrt", 3)
+    c.fn(f, "rcp", 3)
     if trial == "expo":
-        return geometry + 6 + 3
+        c.ops(6 + 3)
+        return
+    c.ops(1 + 1 + 1 + 2 + 4)  # Jastrow: s, is^2, u', u'', cusp-free ee term
+    c.fn(f, "rcp")
     if trial == "pade":
-        return geometry + jastrow + 12 + 6 + 7
+        c.ops(12 + 6 + 7)
+        return
+    c.ops(2 + 1 + 4)  # d, branch of the larger exponential, the pair (t1, t2)
     if trial == "triplet":
-        return geometry + jastrow + swap + 2 + f["expm1"] + 1 + f["rcp"] + 4 + 8 + 6 + 12 + 10 + 2
-    return geometry + jastrow + swap + 2 + f["exp"] + 1 + 1 + f["rcp"] + 6 + 15 + 14 + 6 + 6 + 8 + 4  # pz
+        c.fn(f, "expm1")
+        c.fn(f, "rcp")
+        c.ops(1 + 4 + 8 + 6 + 12 + 10 + 2)
+        return
+    c.fn(f, "exp")
+    c.fn(f, "rcp")
+    c.ops(2 + 5 + 5 + 8 + 14 + 6 + 6 + 8 + 3)  # P, k1, k2, grad Phi / Phi, Lap terms, drift, cross, E_L, sign
+
+
+def count(cfg: dict) -> _Count:
+    prec = cfg.get("precision", "fp64")
+    f = F32 if prec == "mixed" else F64
+    c = _Count()
+    _noise(c, f, cfg.get("noise", "gauss"), int(cfg.get("contract", 1)))
+    _trial(c, f, cfg["trial"])
+    c.ops(12)  # Euler step
+    if cfg.get("drift_limit", 0.0) > 0:
+        c.ops(6 + 1 + 1 + 1 + 1 + 6 + 1)  # |b|^2, 2 a dt |b|^2, 1 + ., 1 + sqrt, 2 / ., scale b, scale e
+        c.fn(f, "sqrt")
+        c.fn(f, "rcp")
+    c.ops(6)  # node test and state commit
+    c.ops(6)  # ln w update in binary64 (conversion, shift by e_ref, quadrature, NaN guard)
+    return c
 
 
 def slots_per_walker_step(cfg: dict) -> float:
-    """Issue slots of one walker step: noise, Euler step, trial evaluation, limiting,
-    node test and state commit, ln w update."""
-    prec = cfg.get("precision", "fp64")
-    f = F32 if prec == "mixed" else F64
-    n = noise_slots(prec, cfg.get("noise", "gauss"), int(cfg.get("contract", 1)))
-    t = trial_slots(prec, cfg["trial"])
-    euler = 12
-    limit = (6 + 1 + 1 + f["sqrt"] + 1 + f["rcp"] + 1 + 6 + 1) if cfg.get("drift_limit", 0.0) > 0 else 0
-    node = 6
-    lnw = 6
-    return float(n + t + euler + limit + node + lnw)
+    """Main-VALU-pipe operations of one walker step."""
+    return float(count(cfg).main)
+
+
+def transcendentals_per_walker_step(cfg: dict) -> float:
+    """binary32 hardware transcendental instructions of one walker step (issued beside the main pipe)."""
+    return float(count(cfg).trans)
 
 
 def fp32_flops_per_walker_step(cfg: dict) -> float:

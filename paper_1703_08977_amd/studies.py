@@ -1,0 +1,172 @@
+"""End-to-end runs of the five workloads on one GPU (energies, errors, timings).
+
+    python -m paper_1703_08977_amd.studies {c1,c2,c3,c4,c5,all} [--seeds N] [--out file.json]
+
+c1  1^1S, exp(-alpha(r1+r2)), alpha = 27/16, 4096 walkers: E_fd(t), E_mixed(0) (variational).
+c2  1^1S, Pade-Jastrow, 2^20 walkers, T = 5, dt in {0.002, 0.001, 0.0005}: window energy
+    per dt over seeds, and its linear extrapolation dt -> 0.
+c3  2^3S triplet (exact node), 2^22 walkers, dt = 0.001, T = 4: mixed vs FP64 on the same
+    seeds (paired difference), absorbed fraction.
+c4  gradient descent of E(T = 2) over (alpha, beta), 2^18 walkers, adjoint gradient.
+c5  P_z (2^1P) "+", 2^24 walkers, dt = 0.0005, T = 6: mixed vs FP64, paired difference,
+    seed-to-seed errors and the time to a 1e-5 Ha statistical error.
+Exact non-relativistic energies (the "Var" row of Table 6) are reported beside.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+EXACT = {"1S": -2.9037243770341195, "3S": -2.17522937823679130, "1P": -2.123843086498093}
+
+
+def _run(cfg, seed, samples_every=None):
+    import torch
+    from . import Ensemble, he_fk_energy
+    from .stats import jackknife
+    c = dict(cfg, seed=seed)
+    se = samples_every or c["sample_every"]
+    e = Ensemble(c)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e.init()
+    ev0.record()
+    s = e.propagate(0, c["n_steps"], se)
+    ev1.record()
+    host = s.cpu().numpy()
+    wall = time.perf_counter() - t0
+    dts = c["dt"] * se
+    e_win = float(he_fk_energy(host, dts, c["e_ref"], "window")[0][0])
+    e_fd = he_fk_energy(host, dts, c["e_ref"], "fd")[0]
+    e_mix = he_fk_energy(host, dts, c["e_ref"], "mixed")[0]
+    _, jk = jackknife(e.block_rows(c["n_steps"], se).cpu().numpy(), dts, c["e_ref"], "window")
+    out = {"seed": seed, "E_window": e_win, "E_window_jackknife": jk, "E_fd_last": float(e_fd[-1]),
+           "E_mixed_0": float(e_mix[0]), "E_mixed_last": float(e_mix[-1]), "alive_fraction": float(host[-1, 4] / host[-1, 6]),
+           "nonfinite": int(host[:, 5].max()), "wall_s": wall, "propagate_s": ev0.elapsed_time(ev1) / 1e3,
+           "ess_last": float(host[-1, 1] ** 2 / host[-1, 3])}
+    del e
+    torch.cuda.empty_cache()
+    print("# %s %s seed %d: E_win %.7f +- %.7f (%.2f s)" % (c["name"], c.get("precision", "fp64"), seed, e_win, jk, wall),
+          file=sys.stderr, flush=True)
+    return out
+
+
+def _mean_se(v):
+    v = np.asarray(v, dtype=np.float64)
+    return float(v.mean()), float(v.std(ddof=1) / math.sqrt(len(v))) if len(v) > 1 else float("nan")
+
+
+def c1(seeds=1):
+    from . import workloads as W
+    cfg = W.get("he_1s_expo_4k")
+    r = _run(cfg, cfg["seed"])
+    return {"workload": cfg["name"], "run": r, "variational_exact": 27.0 ** 2 / 16 ** 2 - 27 * 27 / 128}
+
+
+def c2(seeds=16):
+    from . import workloads as W
+    base = W.get("he_1s_pade_1m")
+    rows = []
+    for dt in base["dts"]:
+        n_steps = int(round(base["T"] / dt))
+        se = int(round(0.05 / dt))
+        cfg = dict(base, dt=dt, n_steps=n_steps, sample_every=se)
+        runs = [_run(cfg, s) for s in range(seeds)]
+        m, se_ = _mean_se([r["E_window"] for r in runs])
+        rows.append({"dt": dt, "E_window": m, "se": se_, "runs": runs})
+        print("# c2 dt=%g E_win=%.7f +- %.7f" % (dt, m, se_), file=sys.stderr, flush=True)
+    x = np.array([r["dt"] for r in rows])
+    y = np.array([r["E_window"] for r in rows])
+    w = 1.0 / np.array([r["se"] for r in rows]) ** 2
+    A = np.stack([np.ones_like(x), x], axis=1)
+    cov = np.linalg.inv(A.T @ (A * w[:, None]))
+    coef = cov @ (A.T @ (w * y))
+    A2 = np.stack([np.ones_like(x), x, x * x], axis=1)
+    coef2 = np.linalg.lstsq(A2 * np.sqrt(w)[:, None], y * np.sqrt(w), rcond=None)[0]
+    return {"workload": base["name"], "per_dt": rows, "E_dt0": float(coef[0]), "E_dt0_se": float(math.sqrt(cov[0, 0])),
+            "slope": float(coef[1]), "quadratic_fit": coef2.tolist(), "exact": EXACT["1S"],
+            "E_dt0_minus_exact": float(coef[0] - EXACT["1S"])}
+
+
+def _paired(name, seeds, **over):
+    from . import workloads as W
+    cfg = W.get(name, **over)
+    mixed = [_run(dict(cfg, precision="mixed"), s) for s in range(seeds)]
+    fp64 = [_run(dict(cfg, precision="fp64"), s) for s in range(seeds)]
+    d = [a["E_window"] - b["E_window"] for a, b in zip(mixed, fp64)]
+    mm, ms = _mean_se([r["E_window"] for r in mixed])
+    fm, fs = _mean_se([r["E_window"] for r in fp64])
+    bm, bs = _mean_se(d)
+    wall_m = float(np.mean([r["wall_s"] for r in mixed]))
+    wall_f = float(np.mean([r["wall_s"] for r in fp64]))
+    sig_m = float(np.std([r["E_window"] for r in mixed], ddof=1)) if seeds > 1 else float("nan")
+    sig_f = float(np.std([r["E_window"] for r in fp64], ddof=1)) if seeds > 1 else float("nan")
+    eps = 1e-5
+    t_m = wall_m * sig_m ** 2 / (eps ** 2 - bm ** 2) if abs(bm) < eps else math.inf
+    t_f = wall_f * sig_f ** 2 / eps ** 2
+    return {"workload": cfg["name"], "seeds": seeds, "mixed": {"E_window": mm, "se": ms, "runs": mixed},
+            "fp64": {"E_window": fm, "se": fs, "runs": fp64},
+            "paired_bias_mixed_minus_fp64": bm, "paired_bias_se": bs,
+            "seed_sigma_mixed": sig_m, "seed_sigma_fp64": sig_f, "wall_mixed_s": wall_m, "wall_fp64_s": wall_f,
+            "time_to_1e-5_Ha_s": {"mixed": t_m, "fp64": t_f, "speedup": t_f / t_m if math.isfinite(t_m) else 0.0}}
+
+
+def c3(seeds=8):
+    r = _paired("he_2tripS_4m", seeds)
+    r["exact"] = EXACT["3S"]
+    r["fp64_minus_exact"] = r["fp64"]["E_window"] - EXACT["3S"]
+    return r
+
+
+def c5(seeds=16):
+    r = _paired("he_2P_pz_16m", seeds)
+    r["exact"] = EXACT["1P"]
+    r["fp64_minus_exact"] = r["fp64"]["E_window"] - EXACT["1P"]
+    return r
+
+
+def c4(seeds=1):
+    from . import workloads as W
+    from .autograd import descend
+    cfg = W.get("he_1s_pade_grad_256k")
+    t0 = time.perf_counter()
+    trace = descend(cfg, score=True, log=lambda r: print("# c4 %s" % json.dumps(r), file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    # spread of E(T) over seeds before and after, at fixed parameters
+    def spread(theta):
+        c = dict(cfg, theta=[theta[0], theta[1], cfg["theta"][2], 0.0])
+        vals = [_run(c, s)["E_fd_last"] for s in range(8)]
+        return _mean_se(vals) + (float(np.std(vals, ddof=1)),)
+    before = spread(cfg["theta"][:2])
+    after = spread([trace[-1]["alpha"], trace[-1]["beta"]])
+    return {"workload": cfg["name"], "trace": trace, "wall_s": wall,
+            "E_T_before": {"mean": before[0], "se": before[1], "sigma": before[2]},
+            "E_T_after": {"mean": after[0], "se": after[1], "sigma": after[2]}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "all"])
+    ap.add_argument("--seeds", type=int, default=None)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    fns = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+    todo = list(fns) if a.which == "all" else [a.which]
+    res = {}
+    for k in todo:
+        res[k] = fns[k]() if a.seeds is None else fns[k](a.seeds)
+        print("# %s done" % k, file=sys.stderr, flush=True)
+    text = json.dumps(res)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text[:2000])
+
+
+if __name__ == "__main__":
+    main()
