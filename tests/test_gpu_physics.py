@@ -1,0 +1,75 @@
+"""Statistical GPU tests of the whole path against closed forms and exact energies
+(5 sigma; sigma from the sample itself or from walker-block jackknife)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1703_08977_amd import workloads as W
+
+from hefk_testutil import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an AMD Instinct GPU")]
+
+EXACT_1S = -2.9037243770341195
+
+
+def test_variational_energy_of_start_ensemble():
+    # |psi|^2 start for exp(-alpha(r1 + r2)), alpha = 27/16, 2^20 walkers:
+    # <E_L> = alpha^2 - 27 alpha / 8, <1/r_i> = alpha, <1/r12> = 5 alpha / 8
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    cfg = W.get("he_1s_expo_4k", n_walkers=1 << 20)
+    e = Ensemble(cfg).init()
+    x, _, el = e.state()
+    a = 27 / 16
+    n = len(el)
+    assert abs(el.mean() - (a * a - 27 * a / 8)) < 5 * el.std() / math.sqrt(n)
+    inv_r = 0.5 * (1 / np.linalg.norm(x[:, :3], axis=1) + 1 / np.linalg.norm(x[:, 3:], axis=1))
+    assert abs(inv_r.mean() - a) < 5 * inv_r.std() / math.sqrt(n)
+    inv_r12 = 1 / np.linalg.norm(x[:, :3] - x[:, 3:], axis=1)
+    assert abs(inv_r12.mean() - 5 * a / 8) < 5 * inv_r12.std() / math.sqrt(n)
+    torch.cuda.synchronize()
+
+
+def test_hydrogen_projection():
+    # two hydrogen atoms with alpha = 0.8: E(0) = alpha^2 - 2 alpha = -0.96; E(T) -> -1
+    from paper_1703_08977_amd import Ensemble, he_fk_energy
+    from paper_1703_08977_amd.stats import jackknife
+    cfg = W.get("hydrogen", theta=[0.8], n_walkers=1 << 20, dt=0.001, n_steps=8000, sample_every=100,
+                e_ref=-0.96, n_metropolis=500)
+    e = Ensemble(cfg).init()
+    s = e.propagate(0, cfg["n_steps"], cfg["sample_every"]).cpu().numpy()
+    mix0 = s[0, 2] / s[0, 1]
+    x, _, el0 = e.state()
+    E, err = jackknife(e.block_rows(cfg["n_steps"], cfg["sample_every"]).cpu().numpy(), 0.1, cfg["e_ref"], "window")
+    assert abs(E - he_fk_energy(s, 0.1, cfg["e_ref"], "window")[0][0]) < 1e-12
+    # E(t) over t in [4, 8]: excited-state contamination of the 1s projection is e^{-(3/8) 4} ~ 0.2 of
+    # the variational error at the window start; the time-step bias is O(dt)
+    assert -1.0 - 5 * err - 0.002 < E < -1.0 + 0.01, (E, err)
+    assert abs(mix0 + 0.96) < 0.01
+
+
+def test_ground_state_energy_bounds():
+    # Pade-Jastrow trial, 2^20 walkers, dt = 0.001, T = 5: within [exact - 5 sigma - dt bias, exact + 2e-3]
+    from paper_1703_08977_amd import Ensemble
+    from paper_1703_08977_amd.stats import jackknife
+    cfg = W.get("he_1s_pade_1m", dt=0.001, n_steps=5000, sample_every=50)
+    e = Ensemble(cfg).init()
+    e.propagate(0, cfg["n_steps"], cfg["sample_every"])
+    E, err = jackknife(e.block_rows(cfg["n_steps"], cfg["sample_every"]).cpu().numpy(), 0.05, cfg["e_ref"], "window")
+    assert EXACT_1S - 5 * err - 5e-4 < E < EXACT_1S + 2e-3, (E, err)
+
+
+def test_exact_trial_has_zero_variance_energy():
+    # Z = 2 without 1/r12 and the exact trial: every estimator gives -4 with zero spread
+    from paper_1703_08977_amd import Ensemble, he_fk_energy
+    cfg = W.get("exact_noee", n_walkers=1 << 16, e_ref=-3.5)
+    e = Ensemble(cfg).init()
+    s = e.propagate(0, 400, 20).cpu().numpy()
+    E = he_fk_energy(s, 0.2, cfg["e_ref"], "fd")[0]
+    assert np.abs(E + 4.0).max() < 1e-10
+    assert np.abs(he_fk_energy(s, 0.2, cfg["e_ref"], "mixed")[0] + 4.0).max() < 1e-12
+    ess = he_fk_energy(s, 0.2, cfg["e_ref"], "fd")[1][:, 1]
+    assert np.abs(ess - (1 << 16)).max() < 1e-6
