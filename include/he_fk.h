@@ -43,7 +43,7 @@ extern "C" {
 #define HE_FK_EALLDEAD (-4)   /* a sample row has no live walker (all absorbed)          */
 #define HE_FK_ESCRATCH (-5)   /* workspace / scratch smaller than the size query returns */
 
-/* ---- trial functions psi_T (theta = {t0, t1, t2, t3}) ---- */
+/* ---- trial functions psi_T (theta = {t0, t1, t2, t3, t4, t5}; t5 unused) ---- */
 /* exp(-t0 (r1 + r2)).  With Z = 2, ee = 0, t0 = 2 it is exact (E_L = -4);
    with Z = 1, ee = 0, t0 = 1 it is two hydrogen atoms (E_L = -1). */
 #define HE_FK_TRIAL_EXPO 0
@@ -56,6 +56,10 @@ extern "C" {
 /* [z2 exp(-t0 r1 - t3 r2) + sym z1 exp(-t0 r2 - t3 r1)] exp(t2 r12 / (1 + t1 r12));
    odd under z -> -z for both electrons (a P_z state, cf. trial function 7) */
 #define HE_FK_TRIAL_PZ 3
+/* [(t4 - r1) exp(-t0 r1 - t3 r2) - (t4 - r2) exp(-t0 r2 - t3 r1)] exp(t2 r12 / (1 + t1 r12)):
+   the paper's trial functions 3-5 for the 2^3S state (r0 = t4, alpha1 = t0, alpha2 = t3;
+   no Jastrow factor when t2 = 0); node r1 = r2 */
+#define HE_FK_TRIAL_TRIPLET_R0 4
 
 #define HE_FK_FP64 0  /* coordinates, drift, E_L, ln w all binary64                       */
 #define HE_FK_MIXED 1 /* coordinates, drift, E_L binary32; ln w, reductions binary64     */
@@ -95,7 +99,7 @@ typedef struct {
     int32_t precision;    /* HE_FK_FP64 or HE_FK_MIXED */
     int32_t n_metropolis; /* Metropolis steps of the start ensemble (>= 0) */
     double Z;             /* nuclear charge (> 0) */
-    double theta[4];      /* trial parameters, see HE_FK_TRIAL_* */
+    double theta[6];      /* trial parameters, see HE_FK_TRIAL_* */
     double dt;            /* time step (> 0) */
     double e_ref;         /* trial energy lambda0 of eq. (4); shifts ln w, cancels in E */
     double metropolis_sigma; /* Metropolis proposal width (> 0) */

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "he_fk_oracle.c")
 _LIB = os.path.join(_HERE, "libhefk_oracle.so")
 
-TRIALS = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3}
+TRIALS = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4}
 NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}
 
@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
         ("trial", ctypes.c_int32), ("sym", ctypes.c_int32), ("ee", ctypes.c_int32),
         ("noise", ctypes.c_int32), ("quad", ctypes.c_int32), ("contract", ctypes.c_int32),
         ("n_metropolis", ctypes.c_int32), ("reserved", ctypes.c_int32),
-        ("Z", ctypes.c_double), ("theta", ctypes.c_double * 4), ("dt", ctypes.c_double),
+        ("Z", ctypes.c_double), ("theta", ctypes.c_double * 6), ("dt", ctypes.c_double),
         ("e_ref", ctypes.c_double), ("metropolis_sigma", ctypes.c_double),
         ("init_sigma", ctypes.c_double), ("drift_limit", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
@@ -104,8 +104,8 @@ def params(cfg: dict) -> _Params:
     p.contract = int(cfg.get("contract", 1))
     p.n_metropolis = int(cfg.get("n_metropolis", 500))
     p.Z = float(cfg.get("Z", 2.0))
-    th = list(cfg["theta"]) + [0.0] * (4 - len(cfg["theta"]))
-    for i in range(4):
+    th = list(cfg["theta"]) + [0.0] * (6 - len(cfg["theta"]))
+    for i in range(6):
         p.theta[i] = float(th[i])
     p.dt = float(cfg["dt"])
     p.e_ref = float(cfg.get("e_ref", 0.0))

@@ -49,6 +49,7 @@
 #define OFK_TRIAL_PADE 1    /* exp(-alpha (r1 + r2)) exp(c r12 / (1 + beta r12))     */
 #define OFK_TRIAL_TRIPLET 2 /* [exp(-A r1 - a r2) - exp(-A r2 - a r1)] * Jastrow     */
 #define OFK_TRIAL_PZ 3      /* [z2 exp(-A r1 - a r2) + s z1 exp(-A r2 - a r1)] * Jastrow */
+#define OFK_TRIAL_TRIPLET_R0 4 /* [(r0 - r1) exp(-A r1 - a r2) - (r0 - r2) exp(-A r2 - a r1)] * Jastrow */
 
 #define OFK_NOISE_GAUSS 0
 #define OFK_NOISE_PM1 1
@@ -70,7 +71,7 @@ typedef struct {
     int32_t n_metropolis; /* Metropolis sweeps of the initial ensemble */
     int32_t reserved;
     double Z;             /* nuclear charge */
-    double theta[4];      /* [0] orbital exponent, [1] Jastrow beta, [2] Jastrow c, [3] second exponent a */
+    double theta[6];      /* [0] orbital exponent, [1] Jastrow beta, [2] Jastrow c, [3] second exponent a, [4] r0 */
     double dt;
     double e_ref;         /* the trial energy lambda0 used as the shift in eq. (4) */
     double metropolis_sigma;
@@ -198,7 +199,7 @@ typedef struct {
 
 static int trial_has_node(const ofk_params* p)
 {
-    return p->trial == OFK_TRIAL_TRIPLET || p->trial == OFK_TRIAL_PZ;
+    return p->trial == OFK_TRIAL_TRIPLET || p->trial == OFK_TRIAL_PZ || p->trial == OFK_TRIAL_TRIPLET_R0;
 }
 
 /*
@@ -251,6 +252,25 @@ void ofk_trial_eval(const ofk_params* p, const double y[6], ofk_eval* out)
         }
         lP1 = ((A * A - 2.0 * A / r1) - q * (a * a - 2.0 * a / r1)) / D;
         lP2 = ((a * a - 2.0 * a / r2) - q * (A * A - 2.0 * A / r2)) / D;
+        lnPhi = -A * r1 - a * r2 + log(fabs(D));
+        sign = (D > 0.0) ? 1 : ((D < 0.0) ? -1 : 0);
+    } else if (p->trial == OFK_TRIAL_TRIPLET_R0) {
+        /* Phi = F(1,2) - F(2,1), F(1,2) = (r0 - r1) exp(-A r1 - a r2) (trial functions 3-5 of
+           the paper).  For u(r) = (r0 - r) exp(-A r): u' = -(1 + A (r0 - r)) exp(-A r),
+           Lap u = [A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r] exp(-A r).  Written per
+           f = exp(-A r1 - a r2) with q = exp((A - a)(r1 - r2)) = g / f. */
+        double r0 = p->theta[4];
+        double q = exp((A - a) * (r1 - r2));
+        double p1 = r0 - r1, p2 = r0 - r2;
+        double D = p1 - p2 * q;
+        double g1 = (-(1.0 + A * p1) + a * p2 * q) / D;
+        double g2 = (-a * p1 + (1.0 + A * p2) * q) / D;
+        for (int k = 0; k < 3; ++k) {
+            gP1[k] = g1 * h1[k];
+            gP2[k] = g2 * h2[k];
+        }
+        lP1 = ((A * (2.0 + A * p1) - 2.0 * (1.0 + A * p1) / r1) - p2 * q * (a * a - 2.0 * a / r1)) / D;
+        lP2 = (p1 * (a * a - 2.0 * a / r2) - q * (A * (2.0 + A * p2) - 2.0 * (1.0 + A * p2) / r2)) / D;
         lnPhi = -A * r1 - a * r2 + log(fabs(D));
         sign = (D > 0.0) ? 1 : ((D < 0.0) ? -1 : 0);
     } else { /* OFK_TRIAL_PZ */

@@ -22,7 +22,7 @@ HE_FK_ENONFINITE = -3
 HE_FK_EALLDEAD = -4
 HE_FK_ESCRATCH = -5
 
-TRIAL = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3}
+TRIAL = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4}
 PRECISION = {"fp64": 0, "mixed": 1}
 NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}
@@ -38,7 +38,7 @@ class HeFkParams(ctypes.Structure):
         ("trial", ctypes.c_int32), ("sym", ctypes.c_int32), ("ee", ctypes.c_int32),
         ("noise", ctypes.c_int32), ("quad", ctypes.c_int32), ("contract", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("n_metropolis", ctypes.c_int32),
-        ("Z", ctypes.c_double), ("theta", ctypes.c_double * 4), ("dt", ctypes.c_double),
+        ("Z", ctypes.c_double), ("theta", ctypes.c_double * 6), ("dt", ctypes.c_double),
         ("e_ref", ctypes.c_double), ("metropolis_sigma", ctypes.c_double), ("init_sigma", ctypes.c_double),
         ("drift_limit", ctypes.c_double), ("seed", ctypes.c_uint64), ("walker_offset", ctypes.c_uint64), ("n_walkers", ctypes.c_int64),
     ]

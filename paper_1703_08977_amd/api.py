@@ -31,8 +31,8 @@ def make_params(cfg: dict, n_walkers: int | None = None, walker_offset: int = 0,
     p.precision = _lib.PRECISION[c.get("precision", "fp64")]
     p.n_metropolis = int(c.get("n_metropolis", 500))
     p.Z = float(c.get("Z", 2.0))
-    th = list(c["theta"]) + [0.0] * (4 - len(c["theta"]))
-    for k in range(4):
+    th = list(c["theta"]) + [0.0] * (6 - len(c["theta"]))
+    for k in range(6):
         p.theta[k] = float(th[k])
     p.dt = float(c["dt"])
     p.e_ref = float(c.get("e_ref", 0.0))

@@ -14,14 +14,14 @@
 
 namespace hefk {
 
-enum : int { TRIAL_EXPO = 0, TRIAL_PADE = 1, TRIAL_TRIPLET = 2, TRIAL_PZ = 3 };
+enum : int { TRIAL_EXPO = 0, TRIAL_PADE = 1, TRIAL_TRIPLET = 2, TRIAL_PZ = 3, TRIAL_TRIPLET_R0 = 4 };
 // noise kinds of the kernels: Gaussian under contract 1, Gaussian under contract 2, +-1 walk
 enum : int { NOISE_G1 = 0, NOISE_G2 = 1, NOISE_PM1 = 2 };
 enum : uint32_t { PHASE_INIT = 0, PHASE_METROPOLIS = 1, PHASE_GAUSS = 2, PHASE_PM1 = 3 };
 
 template <int TRIAL>
 struct has_node {
-    static constexpr bool value = (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_PZ);
+    static constexpr bool value = (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_PZ || TRIAL == TRIAL_TRIPLET_R0);
 };
 
 // ---------------------------------------------------------------------------
@@ -252,11 +252,11 @@ struct NoiseGen {
 // ---------------------------------------------------------------------------
 // Trial functions.  psi = Phi exp(U), U = c r12 / (1 + beta r12).
 // Parameters: A = theta0 (orbital exponent), beta = theta1, c = theta2,
-// a = theta3 (second exponent, TRIPLET and PZ).
+// a = theta3 (second exponent, TRIPLET, PZ, TRIPLET_R0), r0 = theta4 (TRIPLET_R0).
 // ---------------------------------------------------------------------------
 template <typename R>
 struct TrialParams {
-    R A, beta, c, a, Z, ee, sym;
+    R A, beta, c, a, Z, ee, sym, r0;
 };
 
 // Pieces of the geometry every trial uses.
@@ -368,6 +368,34 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el)
         el = (R)-0.5 * (l1 + l2) - j.up * (g1 * c1 - g2 * c2) - j.upp - j.up * j.up + j.ee_term -
              p.Z * (g.i1 + g.i2);
         sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
+    } else if (TRIAL == TRIAL_TRIPLET_R0) {
+        // Phi / max(f, g) = (r0 - r1) t1 - (r0 - r2) t2 = D; with u(r) = (r0 - r) e^{-A r}:
+        //   u'/e^{-A r} = -(1 + A (r0 - r)),  Lap u / e^{-A r} = A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r
+        const Jas<R> j = jastrow(p, g);
+        const R d = (p.A - p.a) * (g.r1 - g.r2);
+        const bool lo = d <= (R)0;
+        const R e = m::exp_(lo ? d : -d);
+        const R t1 = lo ? (R)1 : e;
+        const R t2 = lo ? e : (R)1;
+        const R p1 = p.r0 - g.r1, p2 = p.r0 - g.r2;
+        const R D = p1 * t1 - p2 * t2;
+        const R iD = m::rcp_(D);
+        const R u1 = (R)1 + p.A * p1, u2 = (R)1 + p.A * p2;
+        const R g1 = (-u1 * t1 + p.a * p2 * t2) * iD;
+        const R g2 = (-p.a * p1 * t1 + u2 * t2) * iD;
+        const R l1 = (t1 * (p.A * ((R)2 + p.A * p1) - (R)2 * u1 * g.i1) - p2 * t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
+        const R l2 = (p1 * t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * ((R)2 + p.A * p2) - (R)2 * u2 * g.i2)) * iD;
+        R c1 = 0, c2 = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            b[k] = g1 * g.h1[k] + j.up * g.h12[k];
+            b[3 + k] = g2 * g.h2[k] - j.up * g.h12[k];
+            c1 += g.h1[k] * g.h12[k];
+            c2 += g.h2[k] * g.h12[k];
+        }
+        el = (R)-0.5 * (l1 + l2) - j.up * (g1 * c1 - g2 * c2) - j.upp - j.up * j.up + j.ee_term -
+             p.Z * (g.i1 + g.i2);
+        sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
     } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
@@ -411,7 +439,7 @@ HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
     const double r2 = ::sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
     const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
     const double r12 = ::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    const double U = (TRIAL == TRIAL_EXPO) ? 0.0 : p.c * r12 / (1.0 + p.beta * r12);
+    const double U = (TRIAL == TRIAL_EXPO || p.c == 0.0) ? 0.0 : p.c * r12 / (1.0 + p.beta * r12);
     if (TRIAL == TRIAL_EXPO || TRIAL == TRIAL_PADE) return -p.A * (r1 + r2) + U;
     // ln max(f, g) + ln|Phi / max(f, g)|
     const double d = (p.A - p.a) * (r1 - r2);
@@ -420,6 +448,11 @@ HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
     if (TRIAL == TRIAL_TRIPLET) {
         const double em = ::expm1(lo ? d : -d);
         return lnmax + ::log(::fabs(em)) + U;
+    }
+    if (TRIAL == TRIAL_TRIPLET_R0) {
+        const double e = ::exp(lo ? d : -d);
+        const double D = (p.r0 - r1) * (lo ? 1.0 : e) - (p.r0 - r2) * (lo ? e : 1.0);
+        return lnmax + ::log(::fabs(D)) + U;
     }
     const double e = ::exp(lo ? d : -d);
     const double P = y[5] * (lo ? 1.0 : e) + p.sym * y[2] * (lo ? e : 1.0);

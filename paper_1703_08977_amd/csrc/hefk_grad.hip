@@ -221,6 +221,7 @@ extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const doubl
     a.tp.Z = p->Z;
     a.tp.ee = (double)p->ee;
     a.tp.sym = 1.0;
+    a.tp.r0 = 0.0;
     a.sc.dt = p->dt;
     a.sc.half_dt = 0.5 * p->dt;
     a.sc.e_ref = p->e_ref;

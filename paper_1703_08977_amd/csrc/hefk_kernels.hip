@@ -216,6 +216,7 @@ KernelFn pick_propagate_r(int trial, int noise)
         case TRIAL_EXPO: return pick_propagate<R, TRIAL_EXPO>(noise);
         case TRIAL_PADE: return pick_propagate<R, TRIAL_PADE>(noise);
         case TRIAL_TRIPLET: return pick_propagate<R, TRIAL_TRIPLET>(noise);
+        case TRIAL_TRIPLET_R0: return pick_propagate<R, TRIAL_TRIPLET_R0>(noise);
         default: return pick_propagate<R, TRIAL_PZ>(noise);
     }
 }
@@ -227,6 +228,7 @@ KernelFn pick_init_r(int trial)
         case TRIAL_EXPO: return init_kernel<R, TRIAL_EXPO>;
         case TRIAL_PADE: return init_kernel<R, TRIAL_PADE>;
         case TRIAL_TRIPLET: return init_kernel<R, TRIAL_TRIPLET>;
+        case TRIAL_TRIPLET_R0: return init_kernel<R, TRIAL_TRIPLET_R0>;
         default: return init_kernel<R, TRIAL_PZ>;
     }
 }
@@ -248,7 +250,7 @@ static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int check_params(const he_fk_params* p)
 {
     if (!p) return HE_FK_EINVAL;
-    if (p->trial < HE_FK_TRIAL_EXPO || p->trial > HE_FK_TRIAL_PZ) return HE_FK_EINVAL;
+    if (p->trial < HE_FK_TRIAL_EXPO || p->trial > HE_FK_TRIAL_TRIPLET_R0) return HE_FK_EINVAL;
     if (p->trial == HE_FK_TRIAL_PZ && p->sym != 1 && p->sym != -1) return HE_FK_EINVAL;
     if (p->ee != 0 && p->ee != 1) return HE_FK_EINVAL;
     if (p->noise != HE_FK_NOISE_GAUSS && p->noise != HE_FK_NOISE_PM1) return HE_FK_EINVAL;
@@ -260,7 +262,7 @@ int check_params(const he_fk_params* p)
         !finite_pos(p->init_sigma) || !std::isfinite(p->e_ref) || !(p->drift_limit >= 0.0) ||
         !std::isfinite(p->drift_limit))
         return HE_FK_EINVAL;
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 6; ++k)
         if (!std::isfinite(p->theta[k])) return HE_FK_EINVAL;
     if (!(p->theta[0] > 0.0)) return HE_FK_EINVAL;
     if (p->trial != HE_FK_TRIAL_EXPO && !(p->theta[1] >= 0.0)) return HE_FK_EINVAL;
@@ -280,6 +282,8 @@ static KArgs make_args(const he_fk_params* p)
     a.tpd.Z = p->Z;
     a.tpd.ee = (double)p->ee;
     a.tpd.sym = (double)(p->trial == HE_FK_TRIAL_PZ ? p->sym : 1);
+    a.tpd.r0 = p->theta[4];
+    a.tpf.r0 = (float)a.tpd.r0;
     a.tpf.A = (float)a.tpd.A;
     a.tpf.beta = (float)a.tpd.beta;
     a.tpf.c = (float)a.tpd.c;

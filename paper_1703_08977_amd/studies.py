@@ -10,6 +10,9 @@ c3  2^3S triplet (exact node), 2^22 walkers, dt = 0.001, T = 4: mixed vs FP64 on
 c4  gradient descent of E(T = 2) over (alpha, beta), 2^18 walkers, adjoint gradient.
 c5  P_z (2^1P) "+", 2^24 walkers, dt = 0.0005, T = 6: mixed vs FP64, paired difference,
     seed-to-seed errors and the time to a 1e-5 Ha statistical error.
+paper  the setting of Tables 1 and 2: trial functions 3 and 5, the +-1 walk at scale 30
+    (dt = 1/900), right end-point sum, ln z_t at t = 8..48 and the least-squares fit
+    ln z_t / t = b + a / t, lambda1 = lambda0 - b.
 Exact non-relativistic energies (the "Var" row of Table 6) are reported beside.
 """
 from __future__ import annotations
@@ -149,13 +152,53 @@ def c4(seeds=1):
             "E_T_after": {"mean": after[0], "se": after[1], "sigma": after[2]}}
 
 
+def paper(seeds=8):
+    from . import Ensemble, he_fk_energy
+    from . import workloads as W
+    out = {}
+    for name in ("he_2tripS_fn3_1m", "he_2tripS_fn5_1m"):
+        for prec in ("mixed", "fp64"):
+            cfg = W.get(name, precision=prec)
+            t_fit = np.array(cfg["t_fit"], dtype=np.float64)
+            per_t = int(round(1.0 / cfg["dt"])) // cfg["sample_every"]  # sample rows per unit time
+            lnz, lam1, walls = [], [], []
+            for seed in range(seeds):
+                c = dict(cfg, seed=seed)
+                e = Ensemble(c)
+                t0 = time.perf_counter()
+                e.init()
+                s = e.propagate(0, c["n_steps"], c["sample_every"]).cpu().numpy()
+                walls.append(time.perf_counter() - t0)
+                L = he_fk_energy(s, c["dt"] * c["sample_every"], c["e_ref"], "mixed")[1][:, 0]
+                rows = (t_fit * per_t).astype(int)
+                lz = L[rows]
+                A = np.stack([np.ones_like(t_fit), 1.0 / t_fit], axis=1)
+                b, a = np.linalg.lstsq(A, lz / t_fit, rcond=None)[0]
+                lnz.append(lz)
+                lam1.append(c["e_ref"] - b)
+                print("# paper %s %s seed %d: lambda1 %.7f" % (name, prec, seed, lam1[-1]), file=sys.stderr,
+                      flush=True)
+                del e
+            lnz = np.array(lnz)
+            m, se = _mean_se(lam1)
+            table = [{"t": float(t), "z_t": float(np.exp(lnz[:, i].mean())), "ln_z_t": float(lnz[:, i].mean()),
+                      "ln_z_t_over_t": float(lnz[:, i].mean() / t), "sigma": float(lnz[:, i].std(ddof=1) / t)}
+                     for i, t in enumerate(t_fit)]
+            out["%s_%s" % (name, prec)] = {"lambda0": cfg["e_ref"], "lambda1": m, "lambda1_se": se,
+                                           "lambda1_minus_exact": m - EXACT["3S"], "table": table,
+                                           "wall_s": float(np.mean(walls)), "seeds": seeds}
+    out["paper_lambda1_context"] = {"fn3": -2.17536239, "fn5": -2.1752508}
+    out["exact"] = EXACT["3S"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "all"])
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "paper", "all"])
     ap.add_argument("--seeds", type=int, default=None)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    fns = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+    fns = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "paper": paper}
     todo = list(fns) if a.which == "all" else [a.which]
     res = {}
     for k in todo:

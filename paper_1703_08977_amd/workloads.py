@@ -68,8 +68,22 @@ HE_PZ_16M = dict(
     noise="gauss", quad="trapezoid", contract=2, precision="mixed",
     n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0, drift_limit=1.0, seeds=list(range(16)))
 
+# The paper's own 2^3S runs (Tables 1 and 2): trial functions 3 and 5,
+# (r0 - r1) e^{-alpha1 r1 - alpha2 r2} - (1 <-> 2), the +-1 walk with step 1/scale
+# at scale 30 (dt = 1/900), right end-point Riemann sum, times t = 8..48, e_ref =
+# the printed trial energy lambda0; about a million paths (2^20 walkers).
+PAPER_FN3_1M = dict(
+    name="he_2tripS_fn3_1m", trial="triplet_r0", theta=[1.0, 0.0, 0.0, 2.0, 1.0, 0.0], Z=2.0, ee=1,
+    n_walkers=1 << 20, dt=1.0 / 900.0, n_steps=48 * 900, sample_every=900, seed=0, e_ref=-2.12412661,
+    noise="pm1", quad="right", contract=1, precision="mixed",
+    n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0, t_fit=[8, 16, 24, 32, 40, 48])
+PAPER_FN5_1M = dict(
+    PAPER_FN3_1M, name="he_2tripS_fn5_1m", theta=[0.636748, 0.0, 0.0, 2.002777, 0.73351723, 0.0],
+    e_ref=-2.1742305)
+
 WORKLOADS = {w["name"]: w for w in
-             (HE_GROUND_EXPO_4K, HE_GROUND_PADE_1M, HE_TRIPLET_4M, HE_GRAD_PADE_256K, HE_PZ_16M)}
+             (HE_GROUND_EXPO_4K, HE_GROUND_PADE_1M, HE_TRIPLET_4M, HE_GRAD_PADE_256K, HE_PZ_16M,
+              PAPER_FN3_1M, PAPER_FN5_1M)}
 
 # Closed-form systems.
 # Z = 2 without 1/r12 and the exact product of hydrogenic 1s orbitals: E_L = -4 exactly.

@@ -92,7 +92,7 @@ int main()
         hs.s0_.push_back(b);
         hs.g_.push_back(c);
     }
-    TrialParams<double> tp{th[0], th[1], th[2], th[3], Z, (double)ee, 1.0};
+    TrialParams<double> tp{th[0], th[1], th[2], th[3], Z, (double)ee, 1.0, 0.0};
     StepConst sc{dt, 0.5 * dt, e_ref, quad, 0.0};
     long n;
     if (std::scanf("%ld", &n) != 1) return 2;

@@ -2,7 +2,7 @@
 // checks against the oracle: same start (Metropolis), same noise, same step,
 // same sampling as the propagate kernel, one walker at a time.
 //
-// stdin, line 1: trial sym ee noise contract quad precision n_met Z t0 t1 t2 t3
+// stdin, line 1: trial sym ee noise contract quad precision n_met Z t0 t1 t2 t3 t4
 //                dt e_ref metropolis_sigma init_sigma drift_limit seed n_steps sample_every
 // line 2:        n id_0 ... id_{n-1}
 // stdout, per walker one line: x0[6] x[6] lnw el ell[ns] els[ns]
@@ -16,7 +16,7 @@ using namespace hefk;
 
 struct Cfg {
     int trial, sym, ee, noise, contract, quad, precision, n_met;
-    double Z, th[4], dt, e_ref, msig, isig, limit;
+    double Z, th[5], dt, e_ref, msig, isig, limit;
     unsigned long long seed;
     long n_steps, sample_every;
 };
@@ -32,6 +32,7 @@ TrialParams<R> tparams(const Cfg& c)
     t.Z = (R)c.Z;
     t.ee = (R)c.ee;
     t.sym = (R)(c.trial == TRIAL_PZ ? c.sym : 1);
+    t.r0 = (R)c.th[4];
     return t;
 }
 
@@ -95,6 +96,7 @@ void dispatch(const Cfg& c, unsigned long long g)
         case TRIAL_EXPO: dispatch_noise<R, TRIAL_EXPO>(c, g); break;
         case TRIAL_PADE: dispatch_noise<R, TRIAL_PADE>(c, g); break;
         case TRIAL_TRIPLET: dispatch_noise<R, TRIAL_TRIPLET>(c, g); break;
+        case TRIAL_TRIPLET_R0: dispatch_noise<R, TRIAL_TRIPLET_R0>(c, g); break;
         default: dispatch_noise<R, TRIAL_PZ>(c, g); break;
     }
 }
@@ -102,10 +104,10 @@ void dispatch(const Cfg& c, unsigned long long g)
 int main()
 {
     Cfg c;
-    if (std::scanf("%d %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %ld %ld", &c.trial, &c.sym,
+    if (std::scanf("%d %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %ld %ld", &c.trial, &c.sym,
                    &c.ee, &c.noise, &c.contract, &c.quad, &c.precision, &c.n_met, &c.Z, &c.th[0], &c.th[1],
-                   &c.th[2], &c.th[3], &c.dt, &c.e_ref, &c.msig, &c.isig, &c.limit, &c.seed, &c.n_steps,
-                   &c.sample_every) != 21)
+                   &c.th[2], &c.th[3], &c.th[4], &c.dt, &c.e_ref, &c.msig, &c.isig, &c.limit, &c.seed, &c.n_steps,
+                   &c.sample_every) != 22)
         return 2;
     long n = 0;
     if (std::scanf("%ld", &n) != 1) return 2;

@@ -49,7 +49,7 @@ def _compare(g, r, tol=TOL, node=False):
 
 
 def _has_node(cfg):
-    return cfg["trial"] in ("triplet", "pz")
+    return cfg["trial"] in ("triplet", "pz", "triplet_r0")
 
 
 def test_c1_full_parity():
@@ -75,6 +75,8 @@ CASES = [
     ("he_2P_pz_16m", dict(dt=0.002, precision="fp64", sym=-1, theta=[2.0, 0.3, 0.25, 0.5], contract=2)),
     ("hydrogen", dict()),
     ("he_1s_pade_1m", dict(dt=0.01, drift_limit=0.5, contract=2)),
+    ("he_2tripS_fn3_1m", dict(precision="fp64")),
+    ("he_2tripS_fn5_1m", dict(precision="fp64", noise="gauss", quad="trapezoid", dt=0.002)),
 ]
 
 

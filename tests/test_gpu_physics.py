@@ -73,3 +73,16 @@ def test_exact_trial_has_zero_variance_energy():
     assert np.abs(he_fk_energy(s, 0.2, cfg["e_ref"], "mixed")[0] + 4.0).max() < 1e-12
     ess = he_fk_energy(s, 0.2, cfg["e_ref"], "fd")[1][:, 1]
     assert np.abs(ess - (1 << 16)).max() < 1e-6
+
+
+@pytest.mark.parametrize("name", ["he_2tripS_fn3_1m", "he_2tripS_fn5_1m"])
+def test_paper_trial_energy_lambda0_on_gpu(name):
+    # the trial energies lambda0 printed in Tables 1 and 2 (trial functions 3 and 5),
+    # from the GPU start ensemble of 2^22 walkers in both precisions
+    from paper_1703_08977_amd import Ensemble
+    for prec in ("fp64", "mixed"):
+        cfg = W.get(name, n_walkers=1 << 22, precision=prec)
+        e = Ensemble(cfg).init()
+        _, _, el = e.state()
+        se = el.std() / math.sqrt(len(el))
+        assert abs(el.mean() - cfg["e_ref"]) < 5 * se, (name, prec, el.mean(), cfg["e_ref"], se)

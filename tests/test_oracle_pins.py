@@ -126,7 +126,7 @@ def psi_definition(cfg, y):
     r1 = np.linalg.norm(y[:3])
     r2 = np.linalg.norm(y[3:])
     r12 = np.linalg.norm(y[:3] - y[3:])
-    A, beta, c, a = (list(cfg["theta"]) + [0.0] * 4)[:4]
+    A, beta, c, a = (list(cfg["theta"]) + [0.0] * 6)[:4]
     jas = math.exp(c * r12 / (1.0 + beta * r12))
     if cfg["trial"] == "expo":
         return math.exp(-A * (r1 + r2))
@@ -137,6 +137,9 @@ def psi_definition(cfg, y):
     if cfg["trial"] == "pz":
         s = cfg.get("sym", 1)
         return (y[5] * math.exp(-A * r1 - a * r2) + s * y[2] * math.exp(-A * r2 - a * r1)) * jas
+    if cfg["trial"] == "triplet_r0":
+        r0 = cfg["theta"][4]
+        return ((r0 - r1) * math.exp(-A * r1 - a * r2) - (r0 - r2) * math.exp(-A * r2 - a * r1)) * jas
     raise ValueError(cfg["trial"])
 
 
@@ -174,6 +177,9 @@ TRIAL_CASES = [
     dict(trial="triplet", theta=[1.7, 0.5, 0.4, 0.9], Z=2.0, ee=1),
     dict(trial="pz", sym=1, theta=[2.0, 0.3, 0.5, 0.5], Z=2.0, ee=1),
     dict(trial="pz", sym=-1, theta=[2.0, 0.3, 0.25, 0.5], Z=2.0, ee=1),
+    dict(trial="triplet_r0", theta=[1.0, 0.0, 0.0, 2.0, 1.0], Z=2.0, ee=1),
+    dict(trial="triplet_r0", theta=[0.636748, 0.0, 0.0, 2.002777, 0.73351723], Z=2.0, ee=1),
+    dict(trial="triplet_r0", theta=[1.2, 0.4, 0.25, 1.9, 0.8], Z=2.0, ee=1),
 ]
 
 
@@ -188,8 +194,14 @@ def test_trial_against_finite_differences(cfg):
         r12 = np.linalg.norm(y[:3] - y[3:])
         if min(r1, r2, r12) < 0.25:
             continue
-        if cfg["trial"] == "triplet" and abs(r1 - r2) < 0.2:
+        if cfg["trial"] in ("triplet", "triplet_r0") and abs(r1 - r2) < 0.2:
             continue
+        if cfg["trial"] == "triplet_r0":
+            r0 = cfg["theta"][4]
+            A_, a_ = cfg["theta"][0], cfg["theta"][3]
+            t1, t2 = (r0 - r1) * math.exp(-A_ * r1 - a_ * r2), (r0 - r2) * math.exp(-A_ * r2 - a_ * r1)
+            if abs(t1 - t2) < 0.3 * (abs(t1) + abs(t2)):
+                continue
         if cfg["trial"] == "pz" and abs(y[2]) + abs(y[5]) < 0.2:
             continue
         psi = psi_definition(cfg, y)
@@ -485,3 +497,14 @@ def test_limit_factor_matches_its_textbook_form():
         yp_expected = y + 0.01 * f * e.b + math.sqrt(0.01) * xi
         xo, _, _, _, _ = oracle.propagate(cfg, [9], y[None, :], np.zeros(1), 0, 1, 1)
         assert np.abs(xo[0] - yp_expected).max() < 1e-14
+
+
+
+@pytest.mark.parametrize("name,table", [("he_2tripS_fn3_1m", "Table 1"), ("he_2tripS_fn5_1m", "Table 2")])
+def test_paper_trial_energy_lambda0(name, table):
+    # Tables 1 and 2 print the trial energy lambda0 of trial functions 3 and 5; the
+    # |psi|^2 ensemble's mean local energy must reproduce it (5 sigma, 2^17 walkers)
+    cfg = W.get(name, precision="fp64")
+    _, el = oracle.init(cfg, np.arange(1 << 17))
+    se = el.std() / math.sqrt(len(el))
+    assert abs(el.mean() - cfg["e_ref"]) < 5 * se, (table, el.mean(), cfg["e_ref"], se)
