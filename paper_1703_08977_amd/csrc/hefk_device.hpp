@@ -12,6 +12,8 @@
 
 #define HD __host__ __device__ __forceinline__
 
+#include "hefk_f64math.hpp"
+
 namespace hefk {
 
 enum : int { TRIAL_EXPO = 0, TRIAL_PADE = 1, TRIAL_TRIPLET = 2, TRIAL_PZ = 3, TRIAL_TRIPLET_R0 = 4 };
@@ -25,30 +27,21 @@ struct has_node {
 };
 
 // ---------------------------------------------------------------------------
-// Elementary functions.  binary64: the correctly rounded sqrt and division and
-// the device math library for the transcendentals.  binary32: the hardware
-// approximations (v_sqrt_f32, v_rcp_f32, v_exp_f32, v_log_f32 and
+// Elementary functions.  binary64: the lean functions of hefk_f64math.hpp
+// (a few ulp over the step's arguments) and the library expm1.  binary32: the
+// hardware approximations (v_sqrt_f32, v_rcp_f32, v_exp_f32, v_log_f32 and
 // v_sin_f32 / v_cos_f32, which take their argument in revolutions).
 // ---------------------------------------------------------------------------
 namespace m {
 
-HD double sqrt_(double x) { return ::sqrt(x); }
-HD double rcp_(double x) { return 1.0 / x; }
-HD double exp_(double x) { return ::exp(x); }
+HD double sqrt_(double x) { return f64::sqrt(x); }
+HD double rcp_(double x) { return f64::rcp(x); }
+HD double exp_(double x) { return f64::exp(x); }
 HD double expm1_(double x) { return ::expm1(x); }
-HD double log_(double x) { return ::log(x); }
-HD double neg2log_(double x) { return -2.0 * ::log(x); }
+HD double log_(double x) { return f64::log(x); }
+HD double neg2log_(double x) { return f64::neg2log(x); }
 // sin(2 pi u), cos(2 pi u) for u in (0, 1)
-HD void sincos2pi(double u, double* s, double* c)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    ::sincospi(2.0 * u, s, c);
-#else
-    const double two_pi = 6.283185307179586476925286766559;
-    *s = ::sin(two_pi * u);
-    *c = ::cos(two_pi * u);
-#endif
-}
+HD void sincos2pi(double u, double* s, double* c) { f64::sincos2pi(u, s, c); }
 
 HD float sqrt_(float x)
 {
@@ -435,11 +428,11 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el)
 template <int TRIAL>
 HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
 {
-    const double r1 = ::sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    const double r2 = ::sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+    const double r1 = f64::sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    const double r2 = f64::sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
     const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
-    const double r12 = ::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    const double U = (TRIAL == TRIAL_EXPO || p.c == 0.0) ? 0.0 : p.c * r12 / (1.0 + p.beta * r12);
+    const double r12 = f64::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double U = (TRIAL == TRIAL_EXPO || p.c == 0.0) ? 0.0 : p.c * r12 * f64::rcp(1.0 + p.beta * r12);
     if (TRIAL == TRIAL_EXPO || TRIAL == TRIAL_PADE) return -p.A * (r1 + r2) + U;
     // ln max(f, g) + ln|Phi / max(f, g)|
     const double d = (p.A - p.a) * (r1 - r2);
@@ -447,16 +440,16 @@ HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
     const double lnmax = lo ? (-p.A * r1 - p.a * r2) : (-p.A * r2 - p.a * r1);
     if (TRIAL == TRIAL_TRIPLET) {
         const double em = ::expm1(lo ? d : -d);
-        return lnmax + ::log(::fabs(em)) + U;
+        return lnmax + f64::log(::fabs(em)) + U;
     }
     if (TRIAL == TRIAL_TRIPLET_R0) {
-        const double e = ::exp(lo ? d : -d);
+        const double e = f64::exp(lo ? d : -d);
         const double D = (p.r0 - r1) * (lo ? 1.0 : e) - (p.r0 - r2) * (lo ? e : 1.0);
-        return lnmax + ::log(::fabs(D)) + U;
+        return lnmax + f64::log(::fabs(D)) + U;
     }
-    const double e = ::exp(lo ? d : -d);
+    const double e = f64::exp(lo ? d : -d);
     const double P = y[5] * (lo ? 1.0 : e) + p.sym * y[2] * (lo ? e : 1.0);
-    return lnmax + ::log(::fabs(P)) + U;
+    return lnmax + f64::log(::fabs(P)) + U;
 }
 
 // Start position of one walker (binary64): Y = init_sigma xi(phase 0, vector 0),
@@ -483,7 +476,7 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
         }
         const double u = unit32(w.w[3], 0.0);
         const double lpt = trial_lnpsi<TRIAL>(tp, yt);
-        if (::log(u) < 2.0 * (lpt - lp)) {
+        if (f64::log(u) < 2.0 * (lpt - lp)) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) y[k] = yt[k];
             lp = lpt;
@@ -521,7 +514,7 @@ HD double limit_drift(const StepConst& sc, R b[6], R el)
 #pragma unroll
         for (int k = 0; k < 6; ++k) v2 += b[k] * b[k];
         const R x2 = (R)(2.0 * sc.limit_adt) * v2;
-        const R f = (R)2 / ((R)1 + m::sqrt_((R)1 + x2));
+        const R f = (R)2 * m::rcp_((R)1 + m::sqrt_((R)1 + x2));
 #pragma unroll
         for (int k = 0; k < 6; ++k) b[k] *= f;
         e *= (double)f;

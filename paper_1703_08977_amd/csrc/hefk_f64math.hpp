@@ -1,0 +1,180 @@
+// hefk_f64math.hpp -- binary64 elementary functions for the walker step, written
+// for the arguments the step produces (finite, and positive where a logarithm or
+// a root is taken), without the special-case handling of a general library:
+//
+//   log(x)      x = m 2^e, m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s),
+//               s = (m - 1)/(m + 1), |s| <= 0.1716, by its Taylor series to s^23.
+//   sincos(2 pi u), u in [0, 1): x = 2u = k/2 + y, |y| <= 1/4, t = pi y,
+//               Taylor series of sin t to t^17 and cos t to t^18, quadrant k mod 4.
+//   exp(x)      x <= 0: x = k ln 2 + r, |r| <= ln2/2 (two-part ln 2), Taylor series
+//               of e^r to r^13, then 2^k by exponent scaling.
+//   sqrt(x)     x >= 0: y ~ 1/sqrt(x) from the hardware seed, two Newton steps on
+//               g = x y, h = y/2 (Goldschmidt's coupled iteration), x = 0 -> 0.
+//   1/x         hardware reciprocal seed and two Newton steps, x = 0 -> inf.
+// Each is within a few units in the last place of the correctly rounded value over
+// those arguments.  Host builds use the same code (seeds from the C library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#ifndef HD
+#define HD __host__ __device__ __forceinline__
+#endif
+
+namespace hefk {
+namespace f64 {
+
+HD uint64_t bits(double x)
+{
+    uint64_t b;
+    __builtin_memcpy(&b, &x, 8);
+    return b;
+}
+HD double from_bits(uint64_t b)
+{
+    double x;
+    __builtin_memcpy(&x, &b, 8);
+    return x;
+}
+
+HD double rcp_seed(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcp(x);
+#else
+    return 1.0 / x;
+#endif
+}
+HD double rsq_seed(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsq(x);
+#else
+    return 1.0 / ::sqrt(x);
+#endif
+}
+
+// 1/x: seed and two Newton steps r <- r + r (1 - x r)
+HD double rcp(double x)
+{
+    double r = rcp_seed(x);
+    double e = ::fma(-x, r, 1.0);
+    r = ::fma(r, e, r);
+    e = ::fma(-x, r, 1.0);
+    r = ::fma(r, e, r);
+    return x == 0.0 ? from_bits(bits(x) | 0x7FF0000000000000ull) : r;  // +-inf for +-0
+}
+
+// sqrt(x), x >= 0
+HD double sqrt(double x)
+{
+    const double y = rsq_seed(x);
+    double g = x * y, h = 0.5 * y;
+    double r = ::fma(-g, h, 0.5);
+    g = ::fma(g, r, g);
+    h = ::fma(h, r, h);
+    const double d = ::fma(-g, g, x);
+    g = ::fma(d, h, g);
+    return x == 0.0 ? 0.0 : g;
+}
+
+// log(x), x > 0 finite (0 -> -inf); arguments below 2^-1000 are scaled by 2^100 first
+HD double log(double x)
+{
+    const bool tiny = x < 0x1p-1000;
+    const double xs = tiny ? x * 0x1p100 : x;
+    const uint64_t b = bits(xs);
+    int e = (int)((b >> 52) & 0x7FF) - 1023;
+    double m = from_bits((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull);  // [1, 2)
+    const bool big = m > 1.4142135623730951;
+    m = big ? 0.5 * m : m;
+    e = big ? e + 1 : e;
+    const double s = (m - 1.0) * rcp(m + 1.0);
+    const double z = s * s;
+    // sum_{k=0}^{11} z^k / (2k + 1)
+    double p = 1.0 / 23.0;
+    p = ::fma(p, z, 1.0 / 21.0);
+    p = ::fma(p, z, 1.0 / 19.0);
+    p = ::fma(p, z, 1.0 / 17.0);
+    p = ::fma(p, z, 1.0 / 15.0);
+    p = ::fma(p, z, 1.0 / 13.0);
+    p = ::fma(p, z, 1.0 / 11.0);
+    p = ::fma(p, z, 1.0 / 9.0);
+    p = ::fma(p, z, 1.0 / 7.0);
+    p = ::fma(p, z, 1.0 / 5.0);
+    p = ::fma(p, z, 1.0 / 3.0);
+    const double lm = 2.0 * s + 2.0 * s * z * p;  // 2 s (1 + z p), the leading term kept apart
+    const double ln2_hi = 6.93147180369123816490e-01;  // ln 2 split: high part has 21 trailing zero bits
+    const double ln2_lo = 1.90821492927058770002e-10;
+    const double fe = (double)e - (tiny ? 100.0 : 0.0);
+    const double r = fe * ln2_hi + (lm + fe * ln2_lo);
+    return x == 0.0 ? -INFINITY : r;
+}
+
+// -2 log(x) for the Box-Muller radius
+HD double neg2log(double x) { return -2.0 * log(x); }
+
+// sin(2 pi u), cos(2 pi u) for u in [0, 1)
+HD void sincos2pi(double u, double* s_out, double* c_out)
+{
+    const double x = 2.0 * u;            // exact
+    const double k = ::rint(2.0 * x);    // quadrant index: x = k/2 + y
+    const double y = ::fma(-0.5, k, x);  // exact, |y| <= 1/4
+    const double t = 3.14159265358979323846 * y;
+    const double z = t * t;
+    // sin t = t (1 + sum_{j=1}^{8} (-1)^j z^j / (2j+1)!)
+    double ps = 1.0 / 355687428096000.0;         // + 1/17!
+    ps = ::fma(ps, z, -1.0 / 1307674368000.0);   // - 1/15!
+    ps = ::fma(ps, z, 1.0 / 6227020800.0);       // + 1/13!
+    ps = ::fma(ps, z, -1.0 / 39916800.0);        // - 1/11!
+    ps = ::fma(ps, z, 1.0 / 362880.0);           // + 1/9!
+    ps = ::fma(ps, z, -1.0 / 5040.0);            // - 1/7!
+    ps = ::fma(ps, z, 1.0 / 120.0);              // + 1/5!
+    ps = ::fma(ps, z, -1.0 / 6.0);               // - 1/3!
+    const double sn = ::fma(t * z, ps, t);
+    // cos t = 1 + sum_{j=1}^{9} (-1)^j z^j / (2j)!
+    double pc = -1.0 / 6402373705728000.0;       // - 1/18!
+    pc = ::fma(pc, z, 1.0 / 20922789888000.0);   // + 1/16!
+    pc = ::fma(pc, z, -1.0 / 87178291200.0);     // - 1/14!
+    pc = ::fma(pc, z, 1.0 / 479001600.0);        // + 1/12!
+    pc = ::fma(pc, z, -1.0 / 3628800.0);         // - 1/10!
+    pc = ::fma(pc, z, 1.0 / 40320.0);            // + 1/8!
+    pc = ::fma(pc, z, -1.0 / 720.0);             // - 1/6!
+    pc = ::fma(pc, z, 1.0 / 24.0);               // + 1/4!
+    pc = ::fma(pc, z, -0.5);                     // - 1/2!
+    const double cs = ::fma(z, pc, 1.0);
+    // angle = k pi/2 + t
+    const int q = ((int)k) & 3;
+    *s_out = (q == 0) ? sn : (q == 1) ? cs : (q == 2) ? -sn : -cs;
+    *c_out = (q == 0) ? cs : (q == 1) ? -sn : (q == 2) ? -cs : sn;
+}
+
+// e^x for x <= 0 (and moderate x > 0)
+HD double exp(double x)
+{
+    const double k = ::rint(x * 1.44269504088896340736);  // x / ln 2
+    const double ln2_hi = 6.93147180369123816490e-01;
+    const double ln2_lo = 1.90821492927058770002e-10;
+    const double r = ::fma(-k, ln2_lo, ::fma(-k, ln2_hi, x));  // |r| <= ln2 / 2
+    double p = 1.0 / 6227020800.0;  // 1/13!
+    p = ::fma(p, r, 1.0 / 479001600.0);
+    p = ::fma(p, r, 1.0 / 39916800.0);
+    p = ::fma(p, r, 1.0 / 3628800.0);
+    p = ::fma(p, r, 1.0 / 362880.0);
+    p = ::fma(p, r, 1.0 / 40320.0);
+    p = ::fma(p, r, 1.0 / 5040.0);
+    p = ::fma(p, r, 1.0 / 720.0);
+    p = ::fma(p, r, 1.0 / 120.0);
+    p = ::fma(p, r, 1.0 / 24.0);
+    p = ::fma(p, r, 1.0 / 6.0);
+    p = ::fma(p, r, 0.5);
+    p = ::fma(p, r, 1.0);
+    p = ::fma(p, r, 1.0);
+    return k < -1100.0 ? 0.0 : ::ldexp(p, (int)k);
+}
+
+}  // namespace f64
+}  // namespace hefk

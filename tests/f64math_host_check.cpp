@@ -1,0 +1,43 @@
+// Host build of the binary64 step functions (hefk_f64math.hpp): prints the largest
+// error in units of the last place against the C library over argument sweeps.
+#include <cmath>
+#include <cstdio>
+#include <random>
+
+#include "hefk_f64math.hpp"
+
+static double ulp_err(double got, double ref)
+{
+    if (got == ref) return 0.0;
+    const double u = std::nextafter(std::fabs(ref), INFINITY) - std::fabs(ref);
+    return std::fabs(got - ref) / u;
+}
+
+int main()
+{
+    std::mt19937_64 rng(7);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    double e_log = 0, e_sin = 0, e_cos = 0, e_exp = 0, e_sqrt = 0, e_rcp = 0;
+    for (int i = 0; i < 2000000; ++i) {
+        const double u = (std::floor(U(rng) * 4294967296.0) + 0.5) * 0x1p-32;  // the uniforms of the step
+        e_log = std::fmax(e_log, ulp_err(hefk::f64::log(u), std::log(u)));
+        const double x = std::exp((U(rng) - 0.5) * 60.0);                     // 1e-13 .. 1e13
+        e_log = std::fmax(e_log, ulp_err(hefk::f64::log(x), std::log(x)));
+        double s, c;
+        hefk::f64::sincos2pi(u, &s, &c);
+        // reference: sin/cos of the exactly reduced argument in long double
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)u;
+        e_sin = std::fmax(e_sin, std::fabs((long double)s - std::sin(ang)) / 0x1p-53);
+        e_cos = std::fmax(e_cos, std::fabs((long double)c - std::cos(ang)) / 0x1p-53);
+        const double xe = -U(rng) * 50.0;
+        e_exp = std::fmax(e_exp, ulp_err(hefk::f64::exp(xe), std::exp(xe)));
+        const double xs = x * x;
+        e_sqrt = std::fmax(e_sqrt, ulp_err(hefk::f64::sqrt(xs), std::sqrt(xs)));
+        e_rcp = std::fmax(e_rcp, ulp_err(hefk::f64::rcp(x), 1.0 / x));
+    }
+    std::printf("log %.3f sin %.3f cos %.3f exp %.3f sqrt %.3f rcp %.3f\n", e_log, e_sin, e_cos, e_exp, e_sqrt,
+                e_rcp);
+    std::printf("special %g %g %g %g\n", hefk::f64::log(0.0), hefk::f64::sqrt(0.0), hefk::f64::rcp(0.0),
+                hefk::f64::exp(-800.0));
+    return 0;
+}
