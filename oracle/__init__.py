@@ -23,6 +23,8 @@ _LIB = os.path.join(_HERE, "libhefk_oracle.so")
 TRIALS = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4}
 NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}
+FLAG_PLAIN = 1   # plain Feynman-Kac walk (no drift, integrand V)
+FLAG_BRIDGE = 2  # node-touch (Brownian bridge) survival weight per step
 
 
 def build(force: bool = True) -> str:
@@ -39,7 +41,7 @@ class _Params(ctypes.Structure):
     _fields_ = [
         ("trial", ctypes.c_int32), ("sym", ctypes.c_int32), ("ee", ctypes.c_int32),
         ("noise", ctypes.c_int32), ("quad", ctypes.c_int32), ("contract", ctypes.c_int32),
-        ("n_metropolis", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_metropolis", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("Z", ctypes.c_double), ("theta", ctypes.c_double * 6), ("dt", ctypes.c_double),
         ("e_ref", ctypes.c_double), ("metropolis_sigma", ctypes.c_double),
         ("init_sigma", ctypes.c_double), ("drift_limit", ctypes.c_double), ("seed", ctypes.c_uint64),
@@ -86,11 +88,13 @@ class Eval:
     sign: int
     b: np.ndarray
     el: float
+    V: float
+    gphi2: float
 
 
 class _Eval(ctypes.Structure):
     _fields_ = [("lnpsi", ctypes.c_double), ("sign", ctypes.c_int), ("b", ctypes.c_double * 6),
-                ("el", ctypes.c_double)]
+                ("el", ctypes.c_double), ("V", ctypes.c_double), ("gphi2", ctypes.c_double)]
 
 
 def params(cfg: dict) -> _Params:
@@ -103,6 +107,7 @@ def params(cfg: dict) -> _Params:
     p.quad = QUAD[cfg.get("quad", "trapezoid")]
     p.contract = int(cfg.get("contract", 1))
     p.n_metropolis = int(cfg.get("n_metropolis", 500))
+    p.flags = (FLAG_PLAIN if cfg.get("plain", False) else 0) | (FLAG_BRIDGE if cfg.get("bridge", False) else 0)
     p.Z = float(cfg.get("Z", 2.0))
     th = list(cfg["theta"]) + [0.0] * (6 - len(cfg["theta"]))
     for i in range(6):
@@ -134,7 +139,7 @@ def trial_eval(cfg, y) -> Eval:
     y = np.ascontiguousarray(y, dtype=np.float64)
     e = _Eval()
     L.ofk_trial_eval(ctypes.byref(p), _ptr(y), ctypes.byref(e))
-    return Eval(e.lnpsi, e.sign, np.array(e.b[:]), e.el)
+    return Eval(e.lnpsi, e.sign, np.array(e.b[:]), e.el, e.V, e.gphi2)
 
 
 def gauss6(cfg, phase, blk, g, contract=1):

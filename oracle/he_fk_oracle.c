@@ -23,7 +23,11 @@
  *     exp(-sum V_P dt), kept in the log domain;
  *   - absorption of walkers that cross the trial function's node (excited
  *     states with a known node, section "Path Integral Theory", last paragraph
- *     of the discretisation discussion).
+ *     of the discretisation discussion);
+ *   - optionally the plain Feynman-Kac walk of eqs. (2)-(3) (Brownian walkers,
+ *     integrand V), the non-recurrent process the generalized walk replaces, and
+ *     a Brownian-bridge estimate of node touches inside a step (reflection
+ *     principle), which the paper leaves to an unstated "criterion".
  *
  * Random numbers: Philox4x32-10 from its published definition (Salmon, Moraes,
  * Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11), replacing
@@ -56,6 +60,9 @@
 #define OFK_QUAD_TRAPEZOID 0
 #define OFK_QUAD_RIGHT 1
 
+#define OFK_FLAG_PLAIN 1  /* plain Feynman-Kac: no drift, integrand V - e_ref (eqs. (2)-(3)) */
+#define OFK_FLAG_BRIDGE 2 /* weight each step by the chance that no node was crossed inside it */
+
 #define OFK_PHASE_INIT 0u
 #define OFK_PHASE_METROPOLIS 1u
 #define OFK_PHASE_GAUSS 2u
@@ -69,7 +76,7 @@ typedef struct {
     int32_t quad;         /* OFK_QUAD_* */
     int32_t contract;     /* Gaussian stream contract: 1 or 2 */
     int32_t n_metropolis; /* Metropolis sweeps of the initial ensemble */
-    int32_t reserved;
+    int32_t flags;        /* OFK_FLAG_* */
     double Z;             /* nuclear charge */
     double theta[6];      /* [0] orbital exponent, [1] Jastrow beta, [2] Jastrow c, [3] second exponent a, [4] r0 */
     double dt;
@@ -195,6 +202,8 @@ typedef struct {
     int sign;
     double b[6];
     double el;
+    double V;     /* the potential */
+    double gphi2; /* |grad ln|Phi||^2 of the orbital part (both electrons) */
 } ofk_eval;
 
 static int trial_has_node(const ofk_params* p)
@@ -322,6 +331,10 @@ void ofk_trial_eval(const ofk_params* p, const double y[6], ofk_eval* out)
         out->b[3 + k] = gP2[k] + gU2[k];
     }
     out->el = -0.5 * lap_total + V;
+    out->V = V;
+    double g2 = 0.0;
+    for (int k = 0; k < 3; ++k) g2 += gP1[k] * gP1[k] + gP2[k] * gP2[k];
+    out->gphi2 = g2;
 }
 
 /* ln|psi| only (used by the Metropolis accept test); -inf on the node. */
@@ -414,23 +427,47 @@ static double limit_factor(const ofk_params* p, const double b[6])
 }
 
 /*
+ * Node-crossing correction (flag OFK_FLAG_BRIDGE).  Both end points of a step lie
+ * on the same side of the node, but the continuous path between them may still
+ * have touched it.  For a Brownian bridge of variance dt per coordinate between
+ * points at distances d and d' from a flat boundary, the reflection principle
+ * gives the probability of a touch as exp(-2 d d' / dt).  The distance to the
+ * node is taken as d = |Phi| / |grad Phi| = 1 / |grad ln|Phi|| (Phi the orbital
+ * part, which carries the node; first order in the distance).  The step's weight
+ * is multiplied by the survival probability 1 - exp(-2 d d' / dt), i.e.
+ *   lnw += log(-expm1(-2 / (dt |grad ln Phi(Y)| |grad ln Phi(Y')|))).
+ * Exact for a driftless walk at a flat node; with the drift of the generalized
+ * walk it is the same first-order estimate applied between the end points.
+ */
+static double bridge_log_survival(const ofk_params* p, double g2a, double g2b)
+{
+    double x = 2.0 / (p->dt * sqrt(g2a * g2b));
+    return log(-expm1(-x));
+}
+
+/*
  * State: y[6] and lnw.  lnw = -inf marks a walker absorbed at the node; a NaN
  * marks a walker whose local energy went non-finite (kept NaN from then on).
  * Per step: Y' = Y + dt b(Y) + sqrt(dt) xi_k; if the trial has a node and
  * sign psi(Y') differs from sign psi(Y) (or psi(Y') = 0) the walker is
- * absorbed and frozen; otherwise
- *   trapezoid: lnw -= (dt/2) [(E_L(Y) - e_ref) + (E_L(Y') - e_ref)],
- *   right:     lnw -=  dt    (E_L(Y') - e_ref).
+ * absorbed and frozen; otherwise, with the integrand e(Y) = E_L(Y) - e_ref,
+ *   trapezoid: lnw -= (dt/2) [e(Y) + e(Y')],
+ *   right:     lnw -=  dt    e(Y').
+ * Plain Feynman-Kac (flag OFK_FLAG_PLAIN, eqs. (2)-(3) with f = 1): b = 0 (Brownian
+ * walkers) and e(Y) = V(Y) - e_ref; the start ensemble and the node test still
+ * come from the trial function.  The drift limiting does not apply to it.
  * ell_s / el_s (may be NULL) receive lnw and E_L at steps step0 + s*sample_every.
  */
 void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* lnw, double* el_io,
                           int64_t step0, int64_t n_steps, int64_t sample_every,
                           double* ell_s, double* el_s)
 {
+    const int plain = (p->flags & OFK_FLAG_PLAIN) != 0;
+    const int bridge = (p->flags & OFK_FLAG_BRIDGE) != 0;
     ofk_eval cur;
     ofk_trial_eval(p, y, &cur);
-    double f = limit_factor(p, cur.b);
-    double eb = f * (cur.el - p->e_ref); /* integrand at the current position */
+    double f = plain ? 0.0 : limit_factor(p, cur.b); /* drift scale: 0 for Brownian walkers */
+    double eb = plain ? cur.V - p->e_ref : f * (cur.el - p->e_ref); /* integrand at the current position */
     double w = *lnw;
     double sqdt = sqrt(p->dt);
     int node = trial_has_node(p);
@@ -443,18 +480,19 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
         if (live) {
             double xi[6], yt[6];
             noise6(p, (uint64_t)(step0 + k), g, xi);
-            for (int j = 0; j < 6; ++j) yt[j] = y[j] + p->dt * (f * cur.b[j]) + sqdt * xi[j];
+            for (int j = 0; j < 6; ++j) yt[j] = y[j] + (plain ? 0.0 : p->dt * (f * cur.b[j])) + sqdt * xi[j];
             ofk_eval nxt;
             ofk_trial_eval(p, yt, &nxt);
             if (node && (nxt.sign != cur.sign || nxt.sign == 0)) {
                 w = -INFINITY;
             } else {
-                double fn = limit_factor(p, nxt.b);
-                double ebn = fn * (nxt.el - p->e_ref);
+                double fn = plain ? 0.0 : limit_factor(p, nxt.b);
+                double ebn = plain ? nxt.V - p->e_ref : fn * (nxt.el - p->e_ref);
                 if (p->quad == OFK_QUAD_RIGHT)
                     w = w - p->dt * ebn;
                 else
                     w = w - (0.5 * p->dt) * (eb + ebn);
+                if (bridge && node) w += bridge_log_survival(p, cur.gphi2, nxt.gphi2);
                 if (!isfinite(nxt.el)) w = NAN;
                 memcpy(y, yt, sizeof(double) * 6);
                 cur = nxt;

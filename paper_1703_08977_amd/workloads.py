@@ -3,8 +3,8 @@
 Each workload is a plain dict read by both the HIP path (through the
 binding) and the CPU oracle, so that both draw the same Philox streams.
 Keys:
-  trial        "expo" | "pade" | "triplet" | "pz"
-  theta        [orbital exponent, Jastrow beta, Jastrow c, second exponent a]
+  trial        "expo" | "pade" | "triplet" | "pz" | "triplet_r0"
+  theta        [orbital exponent, Jastrow beta, Jastrow c, second exponent a, r0]
   sym          +1 / -1 (P_z trial: singlet "+" or triplet "-" combination)
   Z, ee        nuclear charge; 1 if the potential holds +1/r12
   dt, n_steps, sample_every, n_walkers, seed
@@ -20,6 +20,10 @@ Keys:
   n_metropolis, metropolis_sigma, init_sigma  (start ensemble ~ |psi|^2)
   drift_limit  a >= 0: drift / integrand limiting near the singular points of
                an inexact trial function (0: the plain discretisation)
+  plain        True: the plain Feynman-Kac walk of eqs. (2)-(3) (no drift,
+               integrand V - e_ref) from the same start ensemble
+  bridge       True: node trials weight each step by the chance that its path
+               did not touch the node (Brownian bridge)
 
 The e_ref values are variational energies of each trial function measured
 with 2^16 Metropolis samples; any value works.
@@ -96,10 +100,19 @@ EXACT_NOEE = dict(
 # Two independent hydrogen atoms (Z = 1, no 1/r12), alpha = 1: E_L = -1 (-1/2 per electron).
 HYDROGEN = dict(EXACT_NOEE, name="hydrogen", theta=[1.0, 0.0, 0.0, 0.0], Z=1.0, e_ref=-1.0)
 
+# Z = 2 without 1/r12, the exact 1s2s triplet 2s(1) 1s(2) - 1s(1) 2s(2) with 2s = (1 - r) e^{-r},
+# 1s = e^{-2r}: the (r0 - r) prefactor trial at (A, a, r0) = (1, 2, 1), no Jastrow.
+# E_L = -Z^2/2 - Z^2/8 = -5/2 exactly; the node r1 = r2 is exact.
+EXACT_TRIPLET_NOEE = dict(
+    EXACT_NOEE, name="exact_triplet_noee", trial="triplet_r0", theta=[1.0, 0.0, 0.0, 2.0, 1.0, 0.0],
+    e_ref=-2.5, contract=2)
+
+CLOSED_FORM = {w["name"]: w for w in (EXACT_NOEE, HYDROGEN, EXACT_TRIPLET_NOEE)}
+
 
 def get(name: str, **overrides) -> dict:
     """A deep copy of a named workload with keys overridden."""
-    src = WORKLOADS.get(name) or {"exact_noee": EXACT_NOEE, "hydrogen": HYDROGEN}[name]
+    src = WORKLOADS.get(name) or CLOSED_FORM[name]
     w = copy.deepcopy(src)
     w.update(overrides)
     return w

@@ -229,6 +229,21 @@ def test_exact_system_local_energy_is_minus_four():
         assert np.allclose(e.b[3:], -2.0 * y[3:] / np.linalg.norm(y[3:]), rtol=0, atol=1e-15)
 
 
+def test_exact_triplet_local_energy_is_minus_five_halves():
+    # 2s(1) 1s(2) - 1s(1) 2s(2) for Z = 2 without 1/r12 is an eigenfunction with
+    # E = -Z^2/2 - Z^2/8; the (r0 - r) prefactor trial at (1, 2, 1) is exactly it
+    cfg = W.get("exact_triplet_noee")
+    rng = np.random.default_rng(9)
+    for _ in range(500):
+        y = rng.normal(size=6)
+        e = oracle.trial_eval(cfg, y)
+        r1, r2 = np.linalg.norm(y[:3]), np.linalg.norm(y[3:])
+        if abs(r1 - r2) < 1e-3:
+            continue
+        assert abs(e.el + 2.5) < 1e-12 * max(1.0, 1.0 / min(r1, r2, abs(r1 - r2)))
+        assert e.sign == (1 if (1 - r1) * math.exp(-r1 - 2 * r2) > (1 - r2) * math.exp(-r2 - 2 * r1) else -1)
+
+
 def test_hydrogen_local_energy():
     cfg = W.get("hydrogen")
     rng = np.random.default_rng(8)
@@ -508,3 +523,118 @@ def test_paper_trial_energy_lambda0(name, table):
     _, el = oracle.init(cfg, np.arange(1 << 17))
     se = el.std() / math.sqrt(len(el))
     assert abs(el.mean() - cfg["e_ref"]) < 5 * se, (table, el.mean(), cfg["e_ref"], se)
+
+
+# --------------------------------------------------------------------------
+# Propagation variants: the plain Feynman-Kac walk of eqs. (2)-(3) and the
+# Brownian-bridge node-touch weight.
+# --------------------------------------------------------------------------
+
+def _potential(cfg, y):
+    r1 = np.linalg.norm(y[..., :3], axis=-1)
+    r2 = np.linalg.norm(y[..., 3:], axis=-1)
+    r12 = np.linalg.norm(y[..., :3] - y[..., 3:], axis=-1)
+    return -cfg["Z"] / r1 - cfg["Z"] / r2 + cfg.get("ee", 1) / r12
+
+
+def test_plain_walk_is_brownian_with_the_potential_as_integrand():
+    # eq. (2): Brownian paths X_k = X_0 + sqrt(dt) sum xi_j (no drift) and the weight
+    # exp(-int V), here by the trapezoid rule along the same path rebuilt from the noise
+    cfg = W.get("he_1s_pade_1m", dt=0.01, plain=True)
+    ids = np.arange(16) * 7 + 3
+    x0, _ = oracle.init(cfg, ids)
+    n = 10
+    x, lnw, el, ell, _ = oracle.propagate(cfg, ids, x0, np.zeros(len(ids)), 0, n, 1)
+    path = [x0]
+    for k in range(n):
+        path.append(path[-1] + math.sqrt(cfg["dt"]) * oracle.noise_bulk(cfg, k, ids))
+    path = np.array(path)                                    # [n+1, walkers, 6]
+    assert np.abs(x - path[-1]).max() < 1e-13
+    v = _potential(cfg, path) - cfg["e_ref"]
+    ln_expected = -np.concatenate([np.zeros((1, len(ids))),
+                                   np.cumsum(0.5 * cfg["dt"] * (v[1:] + v[:-1]), axis=0)])
+    assert np.abs(ell.T - ln_expected).max() < 1e-11
+    # the reported local energy is still E_L of the trial function
+    for i in range(3):
+        assert abs(el[i] - oracle.trial_eval(cfg, x[i]).el) < 1e-12
+
+
+def test_plain_walk_initial_rate_is_the_mean_potential():
+    # d/dt ln <w> at t = 0 is -(<V>_{psi^2} - e_ref) for the plain walk, and
+    # -(<E_L>_{psi^2} - e_ref) for the generalized one.  For exp(-alpha (r1 + r2)):
+    # <V> = -2 Z alpha + 5 alpha / 8, <E_L> = alpha^2 - 27 alpha / 8.
+    alpha = 27.0 / 16.0
+    base = W.get("he_1s_expo_4k", dt=1e-3)
+    ids = np.arange(1 << 15)
+    for plain, exact in ((True, -4 * alpha + 5 * alpha / 8), (False, alpha ** 2 - 27 * alpha / 8)):
+        cfg = dict(base, plain=plain)
+        r = oracle.run(cfg, ids, 1, 1)
+        E = est.e_fd(r["samples"], cfg["dt"], cfg["e_ref"])[-1]
+        se = np.std(_potential(cfg, r["x0"]) if plain else r["el0"]) / math.sqrt(len(ids))
+        assert abs(E - exact) < 5 * se + 0.02, (plain, E, exact, se)
+
+
+def test_bridge_touch_probability_by_brute_force():
+    # A Brownian bridge of variance dt between heights a, b > 0 touches 0 with
+    # probability exp(-2 a b / dt) (reflection principle).  Brute force: fine
+    # sub-steps, with the discrete-monitoring shift 0.5826 sigma sqrt(h) of Broadie,
+    # Glasserman and Kou (1997) applied to the barrier.
+    rng = np.random.default_rng(5)
+    dt, m, n = 1.0, 2000, 8000
+    for a, b in ((0.5, 0.5), (0.3, 0.9)):
+        h = dt / m
+        w = np.cumsum(rng.normal(scale=math.sqrt(h), size=(n, m)), axis=1)
+        t = np.arange(1, m + 1) * h
+        bridge = a + w - (t / dt) * (w[:, -1:] - (b - a))
+        p_mc = float((bridge.min(axis=1) <= 0.0).mean())
+        s = 0.5826 * math.sqrt(h)
+        p = math.exp(-2 * (a + s) * (b + s) / dt)
+        assert abs(p_mc - p) < 5 * math.sqrt(p * (1 - p) / n), (a, b, p_mc, p)
+
+
+@pytest.mark.parametrize("name", ["he_2tripS_4m", "he_2tripS_fn5_1m"])
+def test_node_distance_estimate_near_the_exchange_node(name):
+    # both triplet trials vanish on r1 = r2, whose exact distance from (R1, R2) is
+    # |r1 - r2| / sqrt(2); the estimate 1 / |grad ln|Phi|| agrees to second order
+    cfg = W.get(name, precision="fp64")
+    rng = np.random.default_rng(8)
+    for eps in (1e-2, 1e-3):
+        for _ in range(50):
+            R1 = rng.normal(size=3)
+            r1 = np.linalg.norm(R1)
+            R2 = rng.normal(size=3)
+            R2 *= (r1 + eps * rng.uniform(-1, 1)) / np.linalg.norm(R2)
+            e = oracle.trial_eval(cfg, np.concatenate([R1, R2]))
+            d = abs(r1 - np.linalg.norm(R2)) / math.sqrt(2)
+            assert abs(1 / math.sqrt(e.gphi2) / d - 1) < 5 * eps * eps
+
+
+@pytest.mark.parametrize("plain", [True, False])
+def test_bridge_weight_of_one_step_next_to_the_node(plain):
+    # one step from points 0.002..0.03 from the triplet node: the bridge changes
+    # ln w by log(1 - exp(-2 d d' / dt)) with the exact distances d, d' of the end
+    # points (positions are not changed by it)
+    base = W.get("he_2tripS_4m", dt=1e-4, plain=plain)
+    rng = np.random.default_rng(3)
+    n = 64
+    y = np.zeros((n, 6))
+    for i in range(n):
+        R1 = rng.normal(size=3)
+        r1 = np.linalg.norm(R1)
+        R2 = rng.normal(size=3)
+        R2 *= (r1 + rng.choice([-1, 1]) * rng.uniform(0.003, 0.04)) / np.linalg.norm(R2)
+        y[i] = np.concatenate([R1, R2])
+    ids = np.arange(n) + 100
+    xa, la, _, _, _ = oracle.propagate(dict(base, bridge=False), ids, y, np.zeros(n), 0, 1, 1)
+    xb, lb, _, _, _ = oracle.propagate(dict(base, bridge=True), ids, y, np.zeros(n), 0, 1, 1)
+    assert np.array_equal(xa, xb)
+    live = np.isfinite(la)
+    assert live.sum() > n // 2 and np.array_equal(live, np.isfinite(lb))
+
+    def dist(v):
+        return np.abs(np.linalg.norm(v[:, :3], axis=1) - np.linalg.norm(v[:, 3:], axis=1)) / math.sqrt(2)
+
+    expect = np.log(-np.expm1(-2 * dist(y) * dist(xa) / base["dt"]))
+    got = lb[live] - la[live]
+    assert np.all(got <= 0.0) and got.min() < -1e-3
+    assert np.abs(got - expect[live]).max() < 5e-3 * np.abs(expect[live]).max() + 1e-12
