@@ -70,6 +70,26 @@ extern "C" {
 #define HE_FK_QUAD_TRAPEZOID 0 /* ln w -= dt/2 [(E_L(Y_k) - e_ref) + (E_L(Y_k+1) - e_ref)]  */
 #define HE_FK_QUAD_RIGHT 1     /* ln w -= dt (E_L(Y_k+1) - e_ref): the paper's Riemann sum    */
 
+/* Propagation variants (he_fk_params.flags).
+ *
+ * HE_FK_FLAG_PLAIN: the plain Feynman-Kac walk of eqs. (2)-(3) with f = 1, the
+ *   non-recurrent process that the generalized walk replaces (section "Path
+ *   Integral Theory", first paragraphs): Y' = Y + sqrt(dt) xi (no drift) and the
+ *   integrand V - e_ref in place of E_L - e_ref.  The start ensemble (|psi_T|^2)
+ *   and the node test (absorbing at the node of psi_T) are those of the
+ *   generalized walk; el still reports E_L.  Requires drift_limit = 0.
+ *
+ * HE_FK_FLAG_BRIDGE: node trials only.  Each step that keeps the sign of psi_T
+ *   also multiplies the weight by the chance that the path between its end
+ *   points did not touch the node, 1 - exp(-2 d d' / dt) (Brownian bridge at a
+ *   flat boundary, reflection principle), with the node distance estimated as
+ *   d = 1 / |grad ln|Phi|| from the orbital part Phi of the trial function:
+ *   ln w += log(-expm1(-2 / (dt |grad ln Phi(Y)| |grad ln Phi(Y')|))), in
+ *   binary64.  Exact for the driftless walk at a flat node; an estimate
+ *   between the end points of the generalized walk. */
+#define HE_FK_FLAG_PLAIN 1
+#define HE_FK_FLAG_BRIDGE 2
+
 /*
  * Random stream contract (Philox4x32-10, Salmon et al. SC'11).  The counter of
  * block b is (b, phase, lo32(g), hi32(g)) for global walker id
@@ -98,6 +118,8 @@ typedef struct {
     int32_t contract;     /* 1 or 2 (Gaussian noise only) */
     int32_t precision;    /* HE_FK_FP64 or HE_FK_MIXED */
     int32_t n_metropolis; /* Metropolis steps of the start ensemble (>= 0) */
+    int32_t flags;        /* 0 or an OR of HE_FK_FLAG_* (propagation variants) */
+    int32_t reserved;     /* must be 0 */
     double Z;             /* nuclear charge (> 0) */
     double theta[6];      /* trial parameters, see HE_FK_TRIAL_* */
     double dt;            /* time step (> 0) */

@@ -28,6 +28,8 @@ NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}
 E_METHOD = {"fd": 0, "window": 1, "fit": 2, "mixed": 3}
 GRAD_SCORE = 1
+FLAG_PLAIN = 1   # plain Feynman-Kac walk: no drift, integrand V - e_ref
+FLAG_BRIDGE = 2  # node-touch (Brownian bridge) survival weight per step (node trials)
 
 EXPORTS = ["he_fk_init", "he_fk_propagate_workspace_bytes", "he_fk_propagate", "he_fk_energy",
            "he_fk_grad_scratch_bytes", "he_fk_grad", "he_fk_strerror"]
@@ -38,6 +40,7 @@ class HeFkParams(ctypes.Structure):
         ("trial", ctypes.c_int32), ("sym", ctypes.c_int32), ("ee", ctypes.c_int32),
         ("noise", ctypes.c_int32), ("quad", ctypes.c_int32), ("contract", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("n_metropolis", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("Z", ctypes.c_double), ("theta", ctypes.c_double * 6), ("dt", ctypes.c_double),
         ("e_ref", ctypes.c_double), ("metropolis_sigma", ctypes.c_double), ("init_sigma", ctypes.c_double),
         ("drift_limit", ctypes.c_double), ("seed", ctypes.c_uint64), ("walker_offset", ctypes.c_uint64), ("n_walkers", ctypes.c_int64),

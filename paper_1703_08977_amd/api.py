@@ -30,6 +30,7 @@ def make_params(cfg: dict, n_walkers: int | None = None, walker_offset: int = 0,
     p.contract = int(c.get("contract", 1))
     p.precision = _lib.PRECISION[c.get("precision", "fp64")]
     p.n_metropolis = int(c.get("n_metropolis", 500))
+    p.flags = (_lib.FLAG_PLAIN if c.get("plain", False) else 0) | (_lib.FLAG_BRIDGE if c.get("bridge", False) else 0)
     p.Z = float(c.get("Z", 2.0))
     th = list(c["theta"]) + [0.0] * (6 - len(c["theta"]))
     for k in range(6):

@@ -252,32 +252,30 @@ struct TrialParams {
     R A, beta, c, a, Z, ee, sym, r0;
 };
 
-// Pieces of the geometry every trial uses.
+// Pieces of the geometry every trial uses: the separation vector, the three
+// distances and their inverses, and the projections R1 . D, R2 . D (the unit
+// vectors are never formed: drifts are written as a R1 + b D with scalar a, b).
 template <typename R>
 struct Geo {
-    R h1[3], h2[3], h12[3];  // unit vectors r1/|r1|, r2/|r2|, (r1-r2)/|r1-r2|
+    R D[3];  // r1 - r2
     R r1, r2, r12, i1, i2, i12;
+    R p1, p2;  // R1 . D, R2 . D
 };
 
 template <typename R>
 HD void geometry(const R y[6], Geo<R>& g)
 {
-    const R d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
+    g.D[0] = y[0] - y[3];
+    g.D[1] = y[1] - y[4];
+    g.D[2] = y[2] - y[5];
     g.r1 = m::sqrt_(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     g.r2 = m::sqrt_(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
-    g.r12 = m::sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
+    g.r12 = m::sqrt_(g.D[0] * g.D[0] + g.D[1] * g.D[1] + g.D[2] * g.D[2]);
     g.i1 = m::rcp_(g.r1);
     g.i2 = m::rcp_(g.r2);
     g.i12 = m::rcp_(g.r12);
-    g.h1[0] = y[0] * g.i1;
-    g.h1[1] = y[1] * g.i1;
-    g.h1[2] = y[2] * g.i1;
-    g.h2[0] = y[3] * g.i2;
-    g.h2[1] = y[4] * g.i2;
-    g.h2[2] = y[5] * g.i2;
-    g.h12[0] = d0 * g.i12;
-    g.h12[1] = d1 * g.i12;
-    g.h12[2] = d2 * g.i12;
+    g.p1 = y[0] * g.D[0] + y[1] * g.D[1] + y[2] * g.D[2];
+    g.p2 = y[3] * g.D[0] + y[4] * g.D[1] + y[5] * g.D[2];
 }
 
 // Jastrow pieces: u' = c / s^2, u'' = -2 c beta / s^3, and
@@ -302,92 +300,85 @@ HD Jas<R> jastrow(const TrialParams<R>& p, const Geo<R>& g)
     return j;
 }
 
+// b1 = a1 R1 + w D, b2 = a2 R2 - w D
+template <typename R>
+HD void drift_from(const R y[6], const Geo<R>& g, R a1, R a2, R w, R b[6])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        b[k] = a1 * y[k] + w * g.D[k];
+        b[3 + k] = a2 * y[3 + k] - w * g.D[k];
+    }
+}
+
 // Drift b = grad ln|psi|, local energy E_L = -(1/2) Lap(psi)/psi + V and the sign
-// of psi (0 on the node).  V = -Z/r1 - Z/r2 + ee/r12.
+// of psi (0 on the node).  V = -Z/r1 - Z/r2 + ee/r12.  With h_i = R_i / r_i and
+// h12 = D / r12, the cosines are h1 . h12 = p1 / (r1 r12), h2 . h12 = p2 / (r2 r12).
 //
-// TRIPLET and PZ combine f = e^{-A r1 - a r2} and g = e^{-A r2 - a r1}; with
-// d = (A - a)(r1 - r2), g / f = e^d.  Both are evaluated as Phi / max(f, g):
+// TRIPLET, TRIPLET_R0 and PZ combine f = e^{-A r1 - a r2} and g = e^{-A r2 - a r1};
+// with d = (A - a)(r1 - r2), g / f = e^d.  They are evaluated as Phi / max(f, g):
 // (t1, t2) = (1, e^d) for d <= 0 and (e^{-d}, 1) for d > 0, so no exponential can
 // overflow and every ratio grad Phi / Phi, Lap Phi / Phi is unchanged.
+//
+// gphi2 (optional): |grad ln|Phi||^2 summed over both electrons, Phi the orbital
+// part (the factor that carries the node), for the node-distance estimate.
 template <typename R, int TRIAL>
-HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el)
+HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 = nullptr)
 {
     Geo<R> g;
     geometry(y, g);
     int sign = 1;
     if (TRIAL == TRIAL_EXPO) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            b[k] = -p.A * g.h1[k];
-            b[3 + k] = -p.A * g.h2[k];
-        }
+        drift_from(y, g, -p.A * g.i1, -p.A * g.i2, (R)0, b);
+        if (gphi2) *gphi2 = (R)2 * p.A * p.A;
         // -A^2 + (A - Z)(1/r1 + 1/r2) + ee/r12: exactly -Z^2 for A = Z, ee = 0
         el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + (p.ee != (R)0 ? p.ee * g.i12 : (R)0);
     } else if (TRIAL == TRIAL_PADE) {
+        // grad_i Phi / Phi = -A h_i;  cross term: -A u' (h1 - h2) . h12
         const Jas<R> j = jastrow(p, g);
-        R w = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            b[k] = -p.A * g.h1[k] + j.up * g.h12[k];
-            b[3 + k] = -p.A * g.h2[k] - j.up * g.h12[k];
-            w += (g.h1[k] - g.h2[k]) * g.h12[k];
-        }
+        drift_from(y, g, -p.A * g.i1, -p.A * g.i2, j.up * g.i12, b);
+        if (gphi2) *gphi2 = (R)2 * p.A * p.A;
+        const R w = (g.p1 * g.i1 - g.p2 * g.i2) * g.i12;  // (h1 - h2) . h12
         el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + p.A * j.up * w - j.upp - j.up * j.up + j.ee_term;
-    } else if (TRIAL == TRIAL_TRIPLET) {
-        // Phi / max(f, g) = t1 - t2 = D; with q = t2 / t1 this is the (r1 < r2) form
-        //   g1 = (-A t1 + a t2) / D, g2 = (-a t1 + A t2) / D,
-        //   Lap_1 Phi / Phi = [t1 (A^2 - 2A/r1) - t2 (a^2 - 2a/r1)] / D (and 1 <-> 2 roles for Lap_2)
+    } else if (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_TRIPLET_R0) {
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
         const bool lo = d <= (R)0;
-        const R em = m::expm1_(lo ? d : -d);  // e^{-|d|} - 1, accurate near the node
-        const R e = (R)1 + em;
-        const R t1 = lo ? (R)1 : e;
-        const R t2 = lo ? e : (R)1;
-        const R D = lo ? -em : em;  // t1 - t2 without cancellation
-        const R iD = m::rcp_(D);
-        const R g1 = (-p.A * t1 + p.a * t2) * iD;
-        const R g2 = (-p.a * t1 + p.A * t2) * iD;
-        const R l1 = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) - t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
-        const R l2 = (t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
-        R c1 = 0, c2 = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            b[k] = g1 * g.h1[k] + j.up * g.h12[k];
-            b[3 + k] = g2 * g.h2[k] - j.up * g.h12[k];
-            c1 += g.h1[k] * g.h12[k];
-            c2 += g.h2[k] * g.h12[k];
+        R g1, g2, l1, l2, D;
+        if (TRIAL == TRIAL_TRIPLET) {
+            // Phi / max(f, g) = t1 - t2 = D:
+            //   g1 = (-A t1 + a t2) / D, g2 = (-a t1 + A t2) / D,
+            //   Lap_1 Phi / Phi = [t1 (A^2 - 2A/r1) - t2 (a^2 - 2a/r1)] / D (roles exchanged for Lap_2)
+            const R em = m::expm1_(lo ? d : -d);  // e^{-|d|} - 1, accurate near the node
+            const R e = (R)1 + em;
+            const R t1 = lo ? (R)1 : e;
+            const R t2 = lo ? e : (R)1;
+            D = lo ? -em : em;  // t1 - t2 without cancellation
+            const R iD = m::rcp_(D);
+            g1 = (-p.A * t1 + p.a * t2) * iD;
+            g2 = (-p.a * t1 + p.A * t2) * iD;
+            l1 = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) - t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
+            l2 = (t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
+        } else {
+            // Phi / max(f, g) = (r0 - r1) t1 - (r0 - r2) t2 = D; with u(r) = (r0 - r) e^{-A r}:
+            //   u'/e^{-A r} = -(1 + A (r0 - r)),  Lap u / e^{-A r} = A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r
+            const R e = m::exp_(lo ? d : -d);
+            const R t1 = lo ? (R)1 : e;
+            const R t2 = lo ? e : (R)1;
+            const R q1 = p.r0 - g.r1, q2 = p.r0 - g.r2;
+            D = q1 * t1 - q2 * t2;
+            const R iD = m::rcp_(D);
+            const R u1 = (R)1 + p.A * q1, u2 = (R)1 + p.A * q2;
+            g1 = (-u1 * t1 + p.a * q2 * t2) * iD;
+            g2 = (-p.a * q1 * t1 + u2 * t2) * iD;
+            l1 = (t1 * (p.A * ((R)2 + p.A * q1) - (R)2 * u1 * g.i1) - q2 * t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
+            l2 = (q1 * t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * ((R)2 + p.A * q2) - (R)2 * u2 * g.i2)) * iD;
         }
-        el = (R)-0.5 * (l1 + l2) - j.up * (g1 * c1 - g2 * c2) - j.upp - j.up * j.up + j.ee_term -
-             p.Z * (g.i1 + g.i2);
-        sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
-    } else if (TRIAL == TRIAL_TRIPLET_R0) {
-        // Phi / max(f, g) = (r0 - r1) t1 - (r0 - r2) t2 = D; with u(r) = (r0 - r) e^{-A r}:
-        //   u'/e^{-A r} = -(1 + A (r0 - r)),  Lap u / e^{-A r} = A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r
-        const Jas<R> j = jastrow(p, g);
-        const R d = (p.A - p.a) * (g.r1 - g.r2);
-        const bool lo = d <= (R)0;
-        const R e = m::exp_(lo ? d : -d);
-        const R t1 = lo ? (R)1 : e;
-        const R t2 = lo ? e : (R)1;
-        const R p1 = p.r0 - g.r1, p2 = p.r0 - g.r2;
-        const R D = p1 * t1 - p2 * t2;
-        const R iD = m::rcp_(D);
-        const R u1 = (R)1 + p.A * p1, u2 = (R)1 + p.A * p2;
-        const R g1 = (-u1 * t1 + p.a * p2 * t2) * iD;
-        const R g2 = (-p.a * p1 * t1 + u2 * t2) * iD;
-        const R l1 = (t1 * (p.A * ((R)2 + p.A * p1) - (R)2 * u1 * g.i1) - p2 * t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
-        const R l2 = (p1 * t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * ((R)2 + p.A * p2) - (R)2 * u2 * g.i2)) * iD;
-        R c1 = 0, c2 = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            b[k] = g1 * g.h1[k] + j.up * g.h12[k];
-            b[3 + k] = g2 * g.h2[k] - j.up * g.h12[k];
-            c1 += g.h1[k] * g.h12[k];
-            c2 += g.h2[k] * g.h12[k];
-        }
-        el = (R)-0.5 * (l1 + l2) - j.up * (g1 * c1 - g2 * c2) - j.upp - j.up * j.up + j.ee_term -
-             p.Z * (g.i1 + g.i2);
+        // grad_i Phi / Phi = g_i h_i
+        drift_from(y, g, g1 * g.i1, g2 * g.i2, j.up * g.i12, b);
+        if (gphi2) *gphi2 = g1 * g1 + g2 * g2;
+        const R cross = (g1 * g.p1 * g.i1 - g2 * g.p2 * g.i2) * g.i12;  // g1 h1.h12 - g2 h2.h12
+        el = (R)-0.5 * (l1 + l2) - j.up * cross - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
     } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
@@ -401,27 +392,32 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el)
         const R iP = m::rcp_(P);
         const R k1 = p.A * z2 * t1 + t2 * p.a * z1;  // grad_1 Phi / max = -k1 h1 + t2 zhat
         const R k2 = p.a * z2 * t1 + t2 * p.A * z1;  // grad_2 Phi / max = t1 zhat - k2 h2
-        R gp1[3], gp2[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            gp1[k] = -k1 * g.h1[k] * iP;
-            gp2[k] = -k2 * g.h2[k] * iP;
-        }
-        gp1[2] += t2 * iP;
-        gp2[2] += t1 * iP;
+        const R a1 = -k1 * g.i1 * iP, a2 = -k2 * g.i2 * iP;
+        const R s1 = t2 * iP, s2 = t1 * iP;
+        drift_from(y, g, a1, a2, j.up * g.i12, b);
+        b[2] += s1;
+        b[5] += s2;
+        // |a1 R1 + s1 zhat|^2 + |a2 R2 + s2 zhat|^2
+        if (gphi2)
+            *gphi2 = a1 * a1 * g.r1 * g.r1 + (R)2 * a1 * s1 * z1 + s1 * s1 + a2 * a2 * g.r2 * g.r2 +
+                     (R)2 * a2 * s2 * z2 + s2 * s2;
         const R l1 = (z2 * t1 * (p.A * p.A - (R)2 * p.A * g.i1) + t2 * z1 * (p.a * p.a - (R)4 * p.a * g.i1)) * iP;
         const R l2 = (z2 * t1 * (p.a * p.a - (R)4 * p.a * g.i2) + t2 * z1 * (p.A * p.A - (R)2 * p.A * g.i2)) * iP;
-        R cr = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            b[k] = gp1[k] + j.up * g.h12[k];
-            b[3 + k] = gp2[k] - j.up * g.h12[k];
-            cr += (gp1[k] - gp2[k]) * g.h12[k];
-        }
+        // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12
+        const R cr = (a1 * g.p1 - a2 * g.p2 + (s1 - s2) * g.D[2]) * g.i12;
         el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         sign = (P > (R)0) ? 1 : ((P < (R)0) ? -1 : 0);
     }
     return sign;
+}
+
+// V = -Z/r1 - Z/r2 + ee/r12 (the integrand of the plain walk)
+template <typename R>
+HD R potential(const TrialParams<R>& p, const R y[6])
+{
+    Geo<R> g;
+    geometry(y, g);
+    return -p.Z * (g.i1 + g.i2) + (p.ee != (R)0 ? p.ee * g.i12 : (R)0);
 }
 
 // ln|psi| (binary64; -inf on the node), for the Metropolis start.
@@ -490,9 +486,10 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
 template <typename R>
 struct WalkerState {
     R y[6];
-    R b[6];     // drift used by the next step (limited when drift_limit > 0)
+    R b[6];     // drift used by the next step (limited when drift_limit > 0; 0 for the plain walk)
     R el;       // local energy at y
-    double eb;  // integrand V_P = E_L - e_ref at y (limited when drift_limit > 0)
+    double eb;  // integrand at y: E_L - e_ref (limited when drift_limit > 0), or V - e_ref (plain walk)
+    R gn2;      // |grad ln|Phi||^2 at y (node-touch estimate)
     int sign;
     double lnw;
 };
@@ -501,6 +498,9 @@ struct StepConst {
     double dt, half_dt, e_ref;
     int quad_right;
     double limit_adt;  // drift_limit * dt (0: no limiting)
+    int plain;         // plain Feynman-Kac walk: no drift, integrand V - e_ref
+    int bridge;        // weight each step by the chance that its path missed the node
+    double two_over_dt;
 };
 
 // Drift / integrand limiting near singular points: f = 2 / (1 + sqrt(1 + 2 a dt |b|^2)),
@@ -522,34 +522,57 @@ HD double limit_drift(const StepConst& sc, R b[6], R el)
     return e;
 }
 
-template <typename R, int TRIAL>
+// Integrand at y, and the drift the next step uses.  EXT kernels read the variant
+// flags at run time; the others are the generalized walk only.
+template <typename R, bool EXT>
+HD double integrand(const TrialParams<R>& tp, const StepConst& sc, const R y[6], R b[6], R el)
+{
+    if (EXT && sc.plain) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b[k] = (R)0;
+        return (double)potential<R>(tp, y) - sc.e_ref;
+    }
+    return limit_drift<R>(sc, b, el);
+}
+
+// ln of the chance that a Brownian bridge over one step, between points at node
+// distances d = 1/sqrt(ga) and d' = 1/sqrt(gb), does not touch a flat node:
+// log(1 - exp(-2 d d' / dt)), in binary64.
+HD double bridge_log_survival(const StepConst& sc, double ga, double gb)
+{
+    const double x = sc.two_over_dt * (1.0 / ::sqrt(ga * gb));
+    return ::log(-::expm1(-x));
+}
+
+template <typename R, int TRIAL, bool EXT = false>
 HD void walker_reset(const TrialParams<R>& tp, const StepConst& sc, WalkerState<R>& w)
 {
-    w.sign = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el);
-    w.eb = limit_drift<R>(sc, w.b, w.el);
+    w.sign = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el, EXT ? &w.gn2 : nullptr);
+    w.eb = integrand<R, EXT>(tp, sc, w.y, w.b, w.el);
 }
 
 // Y' = Y + dt b + sqrt(dt) xi; node crossing absorbs (lnw = -inf, frozen);
 // otherwise the quadrature updates ln w in binary64.
-template <typename R, int TRIAL>
+template <typename R, int TRIAL, bool EXT = false>
 HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, R dt_r, R sqdt_r, const R xi[6],
                     WalkerState<R>& w)
 {
     if (w.lnw == -INFINITY) return;
-    R yt[6], bt[6], elt;
+    R yt[6], bt[6], elt, gt = (R)0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) yt[k] = w.y[k] + dt_r * w.b[k] + sqdt_r * xi[k];
-    const int st = trial_eval<R, TRIAL>(tp, yt, bt, elt);
+    const int st = trial_eval<R, TRIAL>(tp, yt, bt, elt, EXT ? &gt : nullptr);
     if (has_node<TRIAL>::value && (st != w.sign || st == 0)) {
         w.lnw = -INFINITY;
         return;
     }
-    const double en = limit_drift<R>(sc, bt, elt);
+    const double en = integrand<R, EXT>(tp, sc, yt, bt, elt);
     double lw;
     if (sc.quad_right)
         lw = w.lnw - sc.dt * en;
     else
         lw = w.lnw - sc.half_dt * (w.eb + en);
+    if (EXT && has_node<TRIAL>::value && sc.bridge) lw += bridge_log_survival(sc, (double)w.gn2, (double)gt);
     if (!__builtin_isfinite((double)elt)) lw = NAN;
     w.lnw = lw;
 #pragma unroll
@@ -559,6 +582,7 @@ HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, R dt_r, R sqd
     }
     w.el = elt;
     w.eb = en;
+    w.gn2 = gt;
     w.sign = st;
 }
 

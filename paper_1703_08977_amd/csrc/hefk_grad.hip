@@ -166,7 +166,7 @@ int layout(const he_fk_params* p, int64_t n_steps, int32_t sample_every, int32_t
     int rc = check_params(p);
     if (rc) return rc;
     if (p->trial != HE_FK_TRIAL_EXPO && p->trial != HE_FK_TRIAL_PADE) return HE_FK_EINVAL;
-    if (p->precision != HE_FK_FP64 || p->drift_limit != 0.0) return HE_FK_EINVAL;
+    if (p->precision != HE_FK_FP64 || p->drift_limit != 0.0 || p->flags != 0) return HE_FK_EINVAL;
     if (n_steps < 1 || sample_every < 1 || ckpt_every < 1) return HE_FK_EINVAL;
     if (n_steps % sample_every || n_steps % ckpt_every) return HE_FK_EINVAL;
     if (ckpt_every % sample_every && sample_every % ckpt_every) return HE_FK_EINVAL;

@@ -109,7 +109,7 @@ __device__ __forceinline__ void sample_row(const KArgs& a, double* part_row, boo
     }
 }
 
-template <typename R, int TRIAL, int NOISE>
+template <typename R, int TRIAL, int NOISE, bool EXT>
 __global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVES_F64) void propagate_kernel(
     const KArgs a)
 {
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVE
 #pragma unroll
         for (int k = 0; k < 6; ++k) w.y[k] = x[(int64_t)k * n + ii];
         w.lnw = a.lnw[ii];
-        walker_reset<R, TRIAL>(tp, a.sc, w);
+        walker_reset<R, TRIAL, EXT>(tp, a.sc, w);
 
         sample_row<R>(a, part, first, valid, w, red);
         if (a.ckpt && valid) {
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVE
         for (int k = 0; k < a.n_steps; ++k) {
             R xi[6];
             noise.draw(st, (uint32_t)(a.step0 + k), xi);
-            walker_step<R, TRIAL>(tp, a.sc, dt_r, sqdt_r, xi, w);
+            walker_step<R, TRIAL, EXT>(tp, a.sc, dt_r, sqdt_r, xi, w);
             if (--until_sample == 0) {
                 until_sample = a.sample_every;
                 sample_row<R>(a, part + (size_t)row * 8, first, valid, w, red);
@@ -199,26 +199,33 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(const double* __restrict_
 // ---------------------------------------------------------------------------
 typedef void (*KernelFn)(KArgs);
 
-template <typename R, int TRIAL>
+template <typename R, int TRIAL, bool EXT>
 KernelFn pick_propagate(int noise)
 {
     switch (noise) {
-        case NOISE_G1: return propagate_kernel<R, TRIAL, NOISE_G1>;
-        case NOISE_G2: return propagate_kernel<R, TRIAL, NOISE_G2>;
-        default: return propagate_kernel<R, TRIAL, NOISE_PM1>;
+        case NOISE_G1: return propagate_kernel<R, TRIAL, NOISE_G1, EXT>;
+        case NOISE_G2: return propagate_kernel<R, TRIAL, NOISE_G2, EXT>;
+        default: return propagate_kernel<R, TRIAL, NOISE_PM1, EXT>;
     }
 }
 
-template <typename R>
-KernelFn pick_propagate_r(int trial, int noise)
+template <typename R, bool EXT>
+KernelFn pick_propagate_t(int trial, int noise)
 {
     switch (trial) {
-        case TRIAL_EXPO: return pick_propagate<R, TRIAL_EXPO>(noise);
-        case TRIAL_PADE: return pick_propagate<R, TRIAL_PADE>(noise);
-        case TRIAL_TRIPLET: return pick_propagate<R, TRIAL_TRIPLET>(noise);
-        case TRIAL_TRIPLET_R0: return pick_propagate<R, TRIAL_TRIPLET_R0>(noise);
-        default: return pick_propagate<R, TRIAL_PZ>(noise);
+        case TRIAL_EXPO: return pick_propagate<R, TRIAL_EXPO, EXT>(noise);
+        case TRIAL_PADE: return pick_propagate<R, TRIAL_PADE, EXT>(noise);
+        case TRIAL_TRIPLET: return pick_propagate<R, TRIAL_TRIPLET, EXT>(noise);
+        case TRIAL_TRIPLET_R0: return pick_propagate<R, TRIAL_TRIPLET_R0, EXT>(noise);
+        default: return pick_propagate<R, TRIAL_PZ, EXT>(noise);
     }
+}
+
+// The generalized walk without variants runs kernels that carry no flag tests.
+template <typename R>
+KernelFn pick_propagate_r(int trial, int noise, int flags)
+{
+    return flags ? pick_propagate_t<R, true>(trial, noise) : pick_propagate_t<R, false>(trial, noise);
 }
 
 template <typename R>
@@ -241,8 +248,8 @@ static int noise_kind(const he_fk_params* p)
 
 static KernelFn propagate_fn(const he_fk_params* p)
 {
-    return p->precision == HE_FK_MIXED ? pick_propagate_r<float>(p->trial, noise_kind(p))
-                                       : pick_propagate_r<double>(p->trial, noise_kind(p));
+    return p->precision == HE_FK_MIXED ? pick_propagate_r<float>(p->trial, noise_kind(p), p->flags)
+                                       : pick_propagate_r<double>(p->trial, noise_kind(p), p->flags);
 }
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -258,6 +265,10 @@ int check_params(const he_fk_params* p)
     if (p->contract != 1 && p->contract != 2) return HE_FK_EINVAL;
     if (p->precision != HE_FK_FP64 && p->precision != HE_FK_MIXED) return HE_FK_EINVAL;
     if (p->n_metropolis < 0) return HE_FK_EINVAL;
+    if ((p->flags & ~(HE_FK_FLAG_PLAIN | HE_FK_FLAG_BRIDGE)) || p->reserved != 0) return HE_FK_EINVAL;
+    if ((p->flags & HE_FK_FLAG_PLAIN) && p->drift_limit != 0.0) return HE_FK_EINVAL;
+    if ((p->flags & HE_FK_FLAG_BRIDGE) && (p->trial == HE_FK_TRIAL_EXPO || p->trial == HE_FK_TRIAL_PADE))
+        return HE_FK_EINVAL;
     if (!finite_pos(p->Z) || !finite_pos(p->dt) || !finite_pos(p->metropolis_sigma) ||
         !finite_pos(p->init_sigma) || !std::isfinite(p->e_ref) || !(p->drift_limit >= 0.0) ||
         !std::isfinite(p->drift_limit))
@@ -296,6 +307,9 @@ static KArgs make_args(const he_fk_params* p)
     a.sc.e_ref = p->e_ref;
     a.sc.quad_right = (p->quad == HE_FK_QUAD_RIGHT);
     a.sc.limit_adt = p->drift_limit * p->dt;
+    a.sc.plain = (p->flags & HE_FK_FLAG_PLAIN) != 0;
+    a.sc.bridge = (p->flags & HE_FK_FLAG_BRIDGE) != 0;
+    a.sc.two_over_dt = 2.0 / p->dt;
     a.dt = p->dt;
     a.sqdt = std::sqrt(p->dt);
     a.dtf = (float)p->dt;

@@ -13,6 +13,13 @@ c5  P_z (2^1P) "+", 2^24 walkers, dt = 0.0005, T = 6: mixed vs FP64, paired diff
 paper  the setting of Tables 1 and 2: trial functions 3 and 5, the +-1 walk at scale 30
     (dt = 1/900), right end-point sum, ln z_t at t = 8..48 and the least-squares fit
     ln z_t / t = b + a / t, lambda1 = lambda0 - b.
+longt  long projection times as in the paper (T = 48) for the ground state (Pade-Jastrow,
+    binary64, 2^20) and the triplet (2^22, mixed): window energy over [T/2, T], the fit
+    L / t = b + a / t over t = 8..48, per dt, and the linear dt -> 0 extrapolation.
+plain  the plain Feynman-Kac walk of eqs. (2)-(3) against the generalized one on the same
+    seeds: He ground state (Pade-Jastrow start) and two hydrogen atoms (exact energy -1).
+bridge the node-touch (Brownian bridge) weight: the exact 1s2s triplet without 1/r12
+    (E = -5/2, exact node) for both walks, and the triplet workload, per dt.
 Exact non-relativistic energies (the "Var" row of Table 6) are reported beside.
 """
 from __future__ import annotations
@@ -28,7 +35,7 @@ import numpy as np
 EXACT = {"1S": -2.9037243770341195, "3S": -2.17522937823679130, "1P": -2.123843086498093}
 
 
-def _run(cfg, seed, samples_every=None):
+def _run(cfg, seed, samples_every=None, keep_L=False):
     import torch
     from . import Ensemble, he_fk_energy
     from .stats import jackknife
@@ -52,6 +59,9 @@ def _run(cfg, seed, samples_every=None):
            "E_mixed_0": float(e_mix[0]), "E_mixed_last": float(e_mix[-1]), "alive_fraction": float(host[-1, 4] / host[-1, 6]),
            "nonfinite": int(host[:, 5].max()), "wall_s": wall, "propagate_s": ev0.elapsed_time(ev1) / 1e3,
            "ess_last": float(host[-1, 1] ** 2 / host[-1, 3])}
+    if keep_L:
+        out["L"] = (host[:, 0] + np.log(host[:, 1]) - np.log(host[:, 6])).tolist()
+        out["alive"] = (host[:, 4] / host[:, 6]).tolist()
     del e
     torch.cuda.empty_cache()
     print("# %s %s seed %d: E_win %.7f +- %.7f (%.2f s)" % (c["name"], c.get("precision", "fp64"), seed, e_win, jk, wall),
@@ -192,13 +202,136 @@ def paper(seeds=8):
     return out
 
 
+def _dt0(rows, key="E_window"):
+    """Weighted linear extrapolation of rows[i][key] (errors rows[i][key + '_se']) to dt = 0."""
+    x = np.array([r["dt"] for r in rows])
+    y = np.array([r[key] for r in rows])
+    w = 1.0 / np.maximum(np.array([r[key + "_se"] for r in rows]), 1e-12) ** 2
+    A = np.stack([np.ones_like(x), x], axis=1)
+    cov = np.linalg.inv(A.T @ (A * w[:, None]))
+    coef = cov @ (A.T @ (w * y))
+    return float(coef[0]), float(math.sqrt(cov[0, 0])), float(coef[1])
+
+
+def _fit_t(L, dts, t_fit, e_ref):
+    """The paper's fit L / t = b + a / t at the given times; E = e_ref - b."""
+    t = np.asarray(t_fit, dtype=np.float64)
+    rows = np.rint(t / dts).astype(int)
+    y = np.asarray(L)[rows] / t
+    A = np.stack([np.ones_like(t), 1.0 / t], axis=1)
+    b, _ = np.linalg.lstsq(A, y, rcond=None)[0]
+    return float(e_ref - b)
+
+
+def longt(seeds=8):
+    from . import workloads as W
+    T, t_fit = 48.0, [8, 16, 24, 32, 40, 48]
+    out = {}
+    for name, prec, dts, exact in (("he_1s_pade_1m", "fp64", [0.002, 0.001, 0.0005], EXACT["1S"]),
+                                   ("he_2tripS_4m", "mixed", [0.002, 0.001, 0.0005], EXACT["3S"])):
+        rows = []
+        for dt in dts:
+            se = int(round(0.5 / dt))
+            cfg = W.get(name, precision=prec, dt=dt, n_steps=int(round(T / dt)), sample_every=se)
+            runs = [_run(cfg, s, keep_L=True) for s in range(seeds)]
+            dts_ = dt * se
+            fits = [_fit_t(r["L"], dts_, t_fit, cfg["e_ref"]) for r in runs]
+            # windows [t/2, t] at t = 8, 16, 32, 48 (the sample rows are dts_ apart)
+            wins = {}
+            for tw in (8, 16, 32, 48):
+                vals = []
+                for r in runs:
+                    L = np.asarray(r["L"])
+                    i0, i1 = int(round(tw / 2 / dts_)), int(round(tw / dts_))
+                    t = np.arange(i0, i1 + 1) * dts_
+                    slope = np.polyfit(t, L[i0:i1 + 1], 1)[0]
+                    vals.append(cfg["e_ref"] - slope)
+                wins[str(tw)] = _mean_se(vals)
+            m, s_ = _mean_se([r["E_window"] for r in runs])
+            fm, fs = _mean_se(fits)
+            row = {"dt": dt, "E_window": m, "E_window_se": s_, "E_fit": fm, "E_fit_se": fs, "windows": wins,
+                   "alive_last": float(np.mean([r["alive_fraction"] for r in runs])),
+                   "ess_last": float(np.mean([r["ess_last"] for r in runs])),
+                   "wall_s": float(np.mean([r["wall_s"] for r in runs])),
+                   "L_mean": np.mean([r["L"] for r in runs], axis=0).tolist()}
+            rows.append(row)
+            print("# longt %s dt=%g E_win=%.7f +- %.7f E_fit=%.7f +- %.7f" % (name, dt, m, s_, fm, fs),
+                  file=sys.stderr, flush=True)
+        e0, e0s, slope = _dt0(rows)
+        f0, f0s, fslope = _dt0(rows, "E_fit")
+        out[name] = {"precision": prec, "T": T, "seeds": seeds, "per_dt": rows, "exact": exact,
+                     "E_window_dt0": e0, "E_window_dt0_se": e0s, "E_window_dt_slope": slope,
+                     "E_window_dt0_minus_exact": e0 - exact, "E_fit_dt0": f0, "E_fit_dt0_se": f0s,
+                     "E_fit_dt0_minus_exact": f0 - exact}
+    return out
+
+
+def plain(seeds=8):
+    from . import workloads as W
+    out = {}
+    for label, cfg, exact in (
+            ("he_1s_pade_1m", W.get("he_1s_pade_1m", dt=0.002, n_steps=2500, sample_every=25), EXACT["1S"]),
+            ("hydrogen_alpha0.8", W.get("hydrogen", theta=[0.8, 0.0, 0.0, 0.0], e_ref=-0.96, n_walkers=1 << 20,
+                                        dt=0.002, n_steps=2500, sample_every=25), -1.0)):
+        res = {}
+        for mode in ("generalized", "plain"):
+            c = dict(cfg, plain=(mode == "plain"))
+            runs = [_run(c, s, keep_L=True) for s in range(seeds)]
+            m, se = _mean_se([r["E_window"] for r in runs])
+            res[mode] = {"E_window": m, "se": se,
+                         "seed_sigma": float(np.std([r["E_window"] for r in runs], ddof=1)),
+                         "ess_last_fraction": float(np.mean([r["ess_last"] for r in runs])) / c["n_walkers"],
+                         "E_fd_curve": np.mean([np.diff(r["L"]) for r in runs], axis=0).tolist()}
+            print("# plain %s %s: E_win %.6f +- %.6f, ESS %.3g" % (label, mode, m, se, res[mode]["ess_last_fraction"]),
+                  file=sys.stderr, flush=True)
+        res["exact"] = exact
+        res["sigma_ratio_plain_over_generalized"] = res["plain"]["seed_sigma"] / res["generalized"]["seed_sigma"]
+        out[label] = res
+    return out
+
+
+def bridge(seeds=4):
+    from . import workloads as W
+    out = {}
+    # the exact 1s2s triplet (Z = 2, no 1/r12): E = -5/2 with the exact node
+    ex = W.get("exact_triplet_noee", n_walkers=1 << 20, T=4.0)
+    rows = []
+    for dt in (0.004, 0.002, 0.001):
+        se = int(round(0.05 / dt))
+        for mode in ("generalized", "plain"):
+            for br in (False, True):
+                c = dict(ex, dt=dt, n_steps=int(round(4.0 / dt)), sample_every=se, plain=(mode == "plain"),
+                         bridge=br)
+                runs = [_run(c, s) for s in range(seeds)]
+                m, s_ = _mean_se([r["E_window"] for r in runs])
+                rows.append({"dt": dt, "walk": mode, "bridge": br, "E_window": m, "se": s_,
+                             "minus_exact": m + 2.5,
+                             "alive_last": float(np.mean([r["alive_fraction"] for r in runs]))})
+                print("# bridge exact dt=%g %s bridge=%d: E %.6f +- %.6f alive %.4f" % (
+                    dt, mode, br, m, s_, rows[-1]["alive_last"]), file=sys.stderr, flush=True)
+    out["exact_triplet_noee"] = {"exact": -2.5, "rows": rows}
+    rows = []
+    for dt in (0.004, 0.002, 0.001):
+        for br in (False, True):
+            c = W.get("he_2tripS_4m", dt=dt, n_steps=int(round(4.0 / dt)), sample_every=int(round(0.05 / dt)),
+                      bridge=br)
+            runs = [_run(c, s) for s in range(seeds)]
+            m, s_ = _mean_se([r["E_window"] for r in runs])
+            rows.append({"dt": dt, "bridge": br, "E_window": m, "se": s_,
+                         "alive_last": float(np.mean([r["alive_fraction"] for r in runs]))})
+            print("# bridge triplet dt=%g bridge=%d: E %.6f +- %.6f" % (dt, br, m, s_), file=sys.stderr, flush=True)
+    out["he_2tripS_4m"] = {"exact": EXACT["3S"], "T": 4.0, "rows": rows}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "paper", "all"])
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "paper", "longt", "plain", "bridge", "all"])
     ap.add_argument("--seeds", type=int, default=None)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    fns = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "paper": paper}
+    fns = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "paper": paper, "longt": longt, "plain": plain,
+           "bridge": bridge}
     todo = list(fns) if a.which == "all" else [a.which]
     res = {}
     for k in todo:

@@ -2,7 +2,7 @@
 // checks against the oracle: same start (Metropolis), same noise, same step,
 // same sampling as the propagate kernel, one walker at a time.
 //
-// stdin, line 1: trial sym ee noise contract quad precision n_met Z t0 t1 t2 t3 t4
+// stdin, line 1: trial sym ee noise contract quad precision n_met flags Z t0 t1 t2 t3 t4
 //                dt e_ref metropolis_sigma init_sigma drift_limit seed n_steps sample_every
 // line 2:        n id_0 ... id_{n-1}
 // stdout, per walker one line: x0[6] x[6] lnw el ell[ns] els[ns]
@@ -15,7 +15,7 @@
 using namespace hefk;
 
 struct Cfg {
-    int trial, sym, ee, noise, contract, quad, precision, n_met;
+    int trial, sym, ee, noise, contract, quad, precision, n_met, flags;
     double Z, th[5], dt, e_ref, msig, isig, limit;
     unsigned long long seed;
     long n_steps, sample_every;
@@ -36,7 +36,7 @@ TrialParams<R> tparams(const Cfg& c)
     return t;
 }
 
-template <typename R, int TRIAL, int NOISE>
+template <typename R, int TRIAL, int NOISE, bool EXT>
 void run_walker(const Cfg& c, unsigned long long g)
 {
     Stream st;
@@ -57,7 +57,10 @@ void run_walker(const Cfg& c, unsigned long long g)
     sc.e_ref = c.e_ref;
     sc.quad_right = c.quad == 1;
     sc.limit_adt = c.limit * c.dt;
-    walker_reset<R, TRIAL>(tp, sc, w);
+    sc.plain = (c.flags & 1) != 0;
+    sc.bridge = (c.flags & 2) != 0;
+    sc.two_over_dt = 2.0 / c.dt;
+    walker_reset<R, TRIAL, EXT>(tp, sc, w);
     const R dt_r = (R)c.dt, sqdt_r = (R)std::sqrt(c.dt);
     std::vector<double> ell, els;
     ell.push_back(w.lnw);
@@ -66,7 +69,7 @@ void run_walker(const Cfg& c, unsigned long long g)
     for (long k = 0; k < c.n_steps; ++k) {
         R xi[6];
         noise.draw(st, (uint32_t)k, xi);
-        walker_step<R, TRIAL>(tp, sc, dt_r, sqdt_r, xi, w);
+        walker_step<R, TRIAL, EXT>(tp, sc, dt_r, sqdt_r, xi, w);
         if ((k + 1) % c.sample_every == 0) {
             ell.push_back(w.lnw);
             els.push_back((double)w.el);
@@ -80,13 +83,20 @@ void run_walker(const Cfg& c, unsigned long long g)
     std::printf("\n");
 }
 
+template <typename R, int TRIAL, bool EXT>
+void dispatch_noise_x(const Cfg& c, unsigned long long g)
+{
+    const int nk = c.noise == 1 ? NOISE_PM1 : (c.contract == 2 ? NOISE_G2 : NOISE_G1);
+    if (nk == NOISE_G1) run_walker<R, TRIAL, NOISE_G1, EXT>(c, g);
+    else if (nk == NOISE_G2) run_walker<R, TRIAL, NOISE_G2, EXT>(c, g);
+    else run_walker<R, TRIAL, NOISE_PM1, EXT>(c, g);
+}
+
 template <typename R, int TRIAL>
 void dispatch_noise(const Cfg& c, unsigned long long g)
 {
-    const int nk = c.noise == 1 ? NOISE_PM1 : (c.contract == 2 ? NOISE_G2 : NOISE_G1);
-    if (nk == NOISE_G1) run_walker<R, TRIAL, NOISE_G1>(c, g);
-    else if (nk == NOISE_G2) run_walker<R, TRIAL, NOISE_G2>(c, g);
-    else run_walker<R, TRIAL, NOISE_PM1>(c, g);
+    if (c.flags) dispatch_noise_x<R, TRIAL, true>(c, g);
+    else dispatch_noise_x<R, TRIAL, false>(c, g);
 }
 
 template <typename R>
@@ -104,10 +114,10 @@ void dispatch(const Cfg& c, unsigned long long g)
 int main()
 {
     Cfg c;
-    if (std::scanf("%d %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %ld %ld", &c.trial, &c.sym,
-                   &c.ee, &c.noise, &c.contract, &c.quad, &c.precision, &c.n_met, &c.Z, &c.th[0], &c.th[1],
-                   &c.th[2], &c.th[3], &c.th[4], &c.dt, &c.e_ref, &c.msig, &c.isig, &c.limit, &c.seed, &c.n_steps,
-                   &c.sample_every) != 22)
+    if (std::scanf("%d %d %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %lf %llu %ld %ld", &c.trial,
+                   &c.sym, &c.ee, &c.noise, &c.contract, &c.quad, &c.precision, &c.n_met, &c.flags, &c.Z, &c.th[0],
+                   &c.th[1], &c.th[2], &c.th[3], &c.th[4], &c.dt, &c.e_ref, &c.msig, &c.isig, &c.limit, &c.seed,
+                   &c.n_steps, &c.sample_every) != 23)
         return 2;
     long n = 0;
     if (std::scanf("%ld", &n) != 1) return 2;

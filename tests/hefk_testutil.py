@@ -76,10 +76,11 @@ def host_harness():
 def host_run(cfg, ids, n_steps, sample_every, precision=0):
     import oracle
     th = list(cfg["theta"]) + [0.0] * 4
-    line = "%d %d %d %d %d %d %d %d %r %r %r %r %r %r %r %r %r %r %r %d %d %d" % (
+    flags = (oracle.FLAG_PLAIN if cfg.get("plain", False) else 0) | (oracle.FLAG_BRIDGE if cfg.get("bridge", False) else 0)
+    line = "%d %d %d %d %d %d %d %d %d %r %r %r %r %r %r %r %r %r %r %r %d %d %d" % (
         oracle.TRIALS[cfg["trial"]], cfg.get("sym", 1), cfg.get("ee", 1),
         1 if cfg.get("noise", "gauss") == "pm1" else 0, cfg.get("contract", 1),
-        1 if cfg.get("quad", "trapezoid") == "right" else 0, precision, cfg.get("n_metropolis", 500),
+        1 if cfg.get("quad", "trapezoid") == "right" else 0, precision, cfg.get("n_metropolis", 500), flags,
         float(cfg["Z"]), *[float(v) for v in th[:5]], float(cfg["dt"]), float(cfg["e_ref"]),
         float(cfg.get("metropolis_sigma", 0.5)), float(cfg.get("init_sigma", 1.0)),
         float(cfg.get("drift_limit", 0.0)), int(cfg["seed"]), n_steps,

@@ -77,6 +77,11 @@ CASES = [
     ("he_1s_pade_1m", dict(dt=0.01, drift_limit=0.5, contract=2)),
     ("he_2tripS_fn3_1m", dict(precision="fp64")),
     ("he_2tripS_fn5_1m", dict(precision="fp64", noise="gauss", quad="trapezoid", dt=0.002)),
+    # variants: plain Feynman-Kac walk, node-touch (bridge) weight
+    ("he_1s_pade_1m", dict(dt=0.002, plain=True)),
+    ("he_2tripS_4m", dict(dt=0.002, precision="fp64", bridge=True)),
+    ("he_2tripS_4m", dict(dt=0.002, precision="fp64", plain=True, bridge=True, noise="pm1")),
+    ("he_2P_pz_16m", dict(dt=0.002, precision="fp64", bridge=True, contract=2)),
 ]
 
 
@@ -142,6 +147,21 @@ def test_mixed_precision_same_start_and_close_paths():
     assert both.mean() > 0.97
     d = np.abs(g["lnw"][both] - r["lnw"][both])
     assert np.median(d) < 1e-4
+
+
+@pytest.mark.parametrize("over", [dict(plain=True), dict(bridge=True), dict(plain=True, bridge=True)])
+def test_mixed_precision_variants_close_to_binary64(over):
+    cfg = W.get("he_2tripS_4m", dt=0.002, precision="mixed", **over)
+    n = 4096
+    g = gpu_run(cfg, n_walkers=n, n_steps=400, sample_every=20)
+    r = oracle.run(dict(cfg, precision="fp64"), np.arange(n), 400, 20)
+    assert np.abs(g["x0"] - r["x0"]).max() <= 2.0**-23 * max(1.0, np.abs(r["x0"]).max())
+    both = np.isfinite(g["lnw"]) & np.isfinite(r["lnw"])
+    assert both.mean() > 0.9
+    assert np.median(np.abs(g["lnw"][both] - r["lnw"][both])) < 1e-4
+    # the log space average stays within the binary32 rounding of the paths
+    Lg, Lr = log_mean_weight(g["samples"]), log_mean_weight(r["samples"])
+    assert np.abs(Lg - Lr).max() < 2e-2
 
 
 def test_exact_system_weights_on_gpu():

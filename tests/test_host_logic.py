@@ -53,6 +53,15 @@ def _bad_params():
     p = api.make_params(base)
     p.walker_offset = (1 << 64) - 10
     yield p
+    p = api.make_params(base)
+    p.flags = 4            # unknown variant bit
+    yield p
+    p = api.make_params(base)
+    p.reserved = 1
+    yield p
+    yield api.make_params(base, plain=True, drift_limit=0.5)   # the limiter belongs to the drifted walk
+    yield api.make_params(base, bridge=True)                   # no node to touch
+    yield api.make_params(W.get("he_1s_pade_1m"), bridge=True)
 
 
 def test_invalid_params_rejected_before_any_launch():
@@ -69,6 +78,24 @@ def test_invalid_params_rejected_before_any_launch():
         rc = _lib.lib().he_fk_propagate(ctypes.byref(p), ctypes.byref(w), s0, ns, se, ctypes.c_void_p(1),
                                         None, 0, ctypes.c_void_p(1), ctypes.c_size_t(1 << 30), None)
         assert rc == _lib.HE_FK_EINVAL
+
+
+def test_variant_flags_accepted_where_defined_and_not_by_the_gradient():
+    ok = [api.make_params(W.get("he_1s_pade_1m"), plain=True),
+          api.make_params(W.get("he_2tripS_4m"), bridge=True),
+          api.make_params(W.get("he_2P_pz_16m", drift_limit=0.0), plain=True, bridge=True)]
+    for p in ok:
+        assert _lib.lib().he_fk_propagate_workspace_bytes(ctypes.byref(p), 10, 5) > 0 or not _gpu_visible()
+    # the adjoint is derived for the generalized walk only
+    p = api.make_params(W.get("he_1s_pade_grad_256k"))
+    assert _lib.lib().he_fk_grad_scratch_bytes(ctypes.byref(p), 100, 50, 50) > 0
+    p = api.make_params(W.get("he_1s_pade_grad_256k"), plain=True)
+    assert _lib.lib().he_fk_grad_scratch_bytes(ctypes.byref(p), 100, 50, 50) == 0
+
+
+def _gpu_visible():
+    import torch
+    return torch.cuda.is_available()
 
 
 def _random_rows(rng, n, N=1000, dead_row=None, bad_row=None):
@@ -167,6 +194,12 @@ HOST_CASES = [
     ("hydrogen", {}),
     ("he_2tripS_fn3_1m", {"precision": "fp64"}),
     ("he_2tripS_fn5_1m", {"precision": "fp64", "noise": "gauss", "contract": 2, "quad": "trapezoid"}),
+    ("he_1s_pade_1m", {"plain": True}),
+    ("he_2tripS_4m", {"dt": 0.005, "plain": True}),
+    ("he_2tripS_4m", {"dt": 0.005, "bridge": True}),
+    ("he_2tripS_4m", {"dt": 0.005, "plain": True, "bridge": True, "noise": "pm1"}),
+    ("he_2P_pz_16m", {"dt": 0.005, "bridge": True}),
+    ("he_2tripS_fn5_1m", {"precision": "fp64", "bridge": True}),
 ]
 
 
@@ -204,3 +237,24 @@ def test_reverse_sweep_host_build_matches_complex_step(over, ckpt_every):
         assert abs(got[d] - ref[d]) <= 1e-11 * max(abs(ref[d]), 1e-3)
     # P = sum_s g_s p_is sums to sum_s g_s over walkers
     assert abs(a[:, 2].sum() - gL.sum()) < 1e-12
+
+
+def test_binary64_step_functions_against_the_c_library():
+    # host build of the binary64 elementary functions of the step (series and Newton
+    # forms written for its argument ranges): errors in units of the last place over
+    # 2e6 arguments each, and the special values the step relies on
+    import shutil
+    import subprocess
+    import tempfile
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    exe = os.path.join(tempfile.mkdtemp(prefix="hefk_f64_"), "f64math_host_check")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.check_call([hipcc, "-O2", "-std=c++17", "--offload-arch=gfx950", "-I",
+                           os.path.join(root, "paper_1703_08977_amd", "csrc"), "-o", exe,
+                           os.path.join(root, "tests", "f64math_host_check.cpp")],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    err = dict(zip(out[0].split()[0::2], map(float, out[0].split()[1::2])))
+    assert err["log"] <= 2.5 and err["exp"] <= 1.5 and err["sqrt"] <= 1.0 and err["rcp"] <= 1.0, err
+    assert err["sin"] <= 2.0 and err["cos"] <= 2.0, err   # absolute, in units of 2^-53
+    assert out[1].split()[1:] == ["-inf", "0", "inf", "0"]
