@@ -98,6 +98,42 @@ def run_leg(cfg, n_steps_timed, n_warmup, seeds):
     return dict(walls=walls, kern=kern, energies=energies, errs=errs)
 
 
+KERNEL_SOURCES = ["include/he_fk.h", "paper_1703_08977_amd/csrc/hefk_device.hpp",
+                  "paper_1703_08977_amd/csrc/hefk_f64math.hpp", "paper_1703_08977_amd/csrc/hefk_reduce.hpp",
+                  "paper_1703_08977_amd/csrc/hefk_kernels.hip", "paper_1703_08977_amd/csrc/build.py"]
+COUNTERS = os.path.join(ROOT, "profiles", "propagate_pz_16m_counters.txt")
+
+
+def source_digest() -> str:
+    """sha256 over the sources of the propagate kernel and its build flags."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def config_key(cfg) -> str:
+    keys = ("name", "trial", "sym", "n_walkers", "n_steps", "sample_every", "precision", "noise", "contract")
+    return " ".join("%s=%s" % (k, cfg.get(k)) for k in keys)
+
+
+def committed_traffic(cfg):
+    """HBM bytes per propagate launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's reading), if it was taken on these kernel sources
+    and this configuration; otherwise None."""
+    try:
+        with open(COUNTERS) as f:
+            kv = dict(ln.split(":", 1) for ln in f.read().splitlines() if ln.startswith("traffic_"))
+    except (OSError, ValueError):
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("traffic_source_digest") != source_digest() or kv.get("traffic_config") != config_key(cfg):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cfg, n_walkers):
     """The oracle (FP64, OpenMP) on a bounded sample of the same workload."""
     import numpy as np
@@ -150,7 +186,7 @@ def main():
     achieved = slots * n * K / kern / 1e12
     peak = PEAK_SLOTS_PER_S / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "propagate_kernel", "slots_per_walker_step": slots,
+            "traffic": committed_traffic(cfg), "kernel": "propagate_kernel", "slots_per_walker_step": slots,
             "transcendentals_per_walker_step": transcendentals_per_walker_step(cfg), "kernel_ms": kern * 1e3}
     fl = fp32_flops_per_walker_step(cfg)
     if fl:

@@ -172,10 +172,12 @@ size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, i
 /*
  * he_fk_propagate: advance every walker over global steps [step0, step0 + n_steps)
  * (drifted diffusion after eq. (4), discretised as in the paper's random-walk
- * construction; absorption at the node for the TRIPLET and PZ trials):
+ * construction; absorption at the node for the TRIPLET, TRIPLET_R0 and PZ trials):
  *   Y' = Y + dt b(Y) + sqrt(dt) xi_k,  b = grad ln|psi_T|;
  *   absorbed (lnw = -inf, frozen) iff sign psi_T(Y') != sign psi_T(Y) or psi_T(Y') = 0;
  *   else ln w updated by the quadrature rule and Y = Y'.
+ * With HE_FK_FLAG_PLAIN, b = 0 and the integrand is V - e_ref; with HE_FK_FLAG_BRIDGE
+ * the node-touch survival term is added to ln w after the quadrature.
  * samples [n_steps / sample_every + 1][8] (device, binary64): row s is the
  * space average at step step0 + s * sample_every (row 0 = the state on entry):
  *   (m, S0, S1, S2, n_alive, n_nonfinite, n_total, 0) with m = max ln w over

@@ -69,27 +69,43 @@ def _noise(c: _Count, f, noise: str, contract: int):
 
 
 def _trial(c: _Count, f, trial: str):
-    # geometry: differences, three squared norms, sqrt, reciprocal, unit vectors
-    c.ops(3 + 3 * 3 + 9)
+    # geometry: D = R1 - R2 (3), three squared norms (3 x 3), sqrt and reciprocal of each,
+    # the projections R1.D and R2.D (2 x 3)
+    c.ops(3 + 3 * 3 + 2 * 3)
     c.fn(f, "sqrt", 3)
     c.fn(f, "rcp", 3)
+    drift = 6 * 2  # b1 = a1 R1 + w D, b2 = a2 R2 - w D: a multiply and a fused add per coordinate
     if trial == "expo":
-        c.ops(6 + 3)
+        # a_i = -A / r_i (2), b = a_i R_i (6), E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + ee/r12 (3)
+        c.ops(2 + 6 + 3)
         return
-    c.ops(1 + 1 + 1 + 2 + 4)  # Jastrow: s, is^2, u', u'', cusp-free ee term
+    # Jastrow: 1 + beta r12 and its reciprocal, 1/s^2, u', u'', the cusp-free ee term (4)
+    c.ops(1 + 1 + 1 + 2 + 4)
     c.fn(f, "rcp")
     if trial == "pade":
-        c.ops(12 + 6 + 7)
+        # a_i (2), w = u'/r12 (1), drift, cosine difference (3),
+        # E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + A u' cos - u'' - u'^2 + ee term (7)
+        c.ops(2 + 1 + drift + 3 + 7)
         return
-    c.ops(2 + 1 + 4)  # d, branch of the larger exponential, the pair (t1, t2)
+    # d = (A - a)(r1 - r2) (2), its sign (1), the argument -|d| (2), the pair (t1, t2) (2)
+    c.ops(2 + 1 + 2 + 2)
     if trial == "triplet":
         c.fn(f, "expm1")
         c.fn(f, "rcp")
-        c.ops(1 + 4 + 8 + 6 + 12 + 10 + 2)
+        # e = 1 + em, D (2), g1, g2 (2 x 3), Laplacian ratios (2 x 6), g_i / r_i (2), w (1), drift,
+        # cross term (5), E_L (8), sign (3)
+        c.ops(1 + 2 + 6 + 12 + 2 + 1 + drift + 5 + 8 + 3)
         return
     c.fn(f, "exp")
     c.fn(f, "rcp")
-    c.ops(2 + 5 + 5 + 8 + 14 + 6 + 6 + 8 + 3)  # P, k1, k2, grad Phi / Phi, Lap terms, drift, cross, E_L, sign
+    if trial == "triplet_r0":
+        # q_i = r0 - r_i, u_i = 1 + A q_i (4), D (2), g1, g2 (2 x 4), Laplacian ratios (2 x 8),
+        # g_i / r_i (2), w (1), drift, cross term (5), E_L (8), sign (3)
+        c.ops(4 + 2 + 8 + 16 + 2 + 1 + drift + 5 + 8 + 3)
+        return
+    # P_z: sym t2 (1), P (2), k1, k2 (2 x 4), a1, a2 (2 x 2), s1, s2 (2), w (1), drift, z terms (2),
+    # Laplacian ratios (2 x 7), cross term (5), E_L (8), sign (3)
+    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 14 + 5 + 8 + 3)
 
 
 def count(cfg: dict) -> _Count:
@@ -122,6 +138,6 @@ def fp32_flops_per_walker_step(cfg: dict) -> float:
     """binary32 floating-point operations of one mixed step (fma = 2, transcendental = 1)."""
     if cfg.get("precision", "fp64") != "mixed":
         return 0.0
-    base = {"expo": 50, "pade": 85, "triplet": 125, "pz": 140}[cfg["trial"]]
+    base = {"expo": 50, "pade": 85, "triplet": 125, "triplet_r0": 130, "pz": 140}[cfg["trial"]]
     noise = 0 if cfg.get("noise", "gauss") == "pm1" else 3 * 6 + 6
     return float(12 * 2 + base + noise)

@@ -166,7 +166,7 @@ def paper(seeds=8):
     from . import Ensemble, he_fk_energy
     from . import workloads as W
     out = {}
-    for name in ("he_2tripS_fn3_1m", "he_2tripS_fn5_1m"):
+    for name in ("he_2tripS_fn3_1m", "he_2tripS_fn4_1m", "he_2tripS_fn5_1m"):
         for prec in ("mixed", "fp64"):
             cfg = W.get(name, precision=prec)
             t_fit = np.array(cfg["t_fit"], dtype=np.float64)
@@ -297,7 +297,7 @@ def bridge(seeds=4):
     ex = W.get("exact_triplet_noee", n_walkers=1 << 20, T=4.0)
     rows = []
     for dt in (0.004, 0.002, 0.001):
-        se = int(round(0.05 / dt))
+        se = int(round(0.04 / dt))
         for mode in ("generalized", "plain"):
             for br in (False, True):
                 c = dict(ex, dt=dt, n_steps=int(round(4.0 / dt)), sample_every=se, plain=(mode == "plain"),
@@ -313,7 +313,7 @@ def bridge(seeds=4):
     rows = []
     for dt in (0.004, 0.002, 0.001):
         for br in (False, True):
-            c = W.get("he_2tripS_4m", dt=dt, n_steps=int(round(4.0 / dt)), sample_every=int(round(0.05 / dt)),
+            c = W.get("he_2tripS_4m", dt=dt, n_steps=int(round(4.0 / dt)), sample_every=int(round(0.04 / dt)),
                       bridge=br)
             runs = [_run(c, s) for s in range(seeds)]
             m, s_ = _mean_se([r["E_window"] for r in runs])
@@ -321,6 +321,21 @@ def bridge(seeds=4):
                          "alive_last": float(np.mean([r["alive_fraction"] for r in runs]))})
             print("# bridge triplet dt=%g bridge=%d: E %.6f +- %.6f" % (dt, br, m, s_), file=sys.stderr, flush=True)
     out["he_2tripS_4m"] = {"exact": EXACT["3S"], "T": 4.0, "rows": rows}
+    # survival of Brownian walkers in their nodal pocket (r1 > r2 or r1 < r2) up to T = 0.5: the
+    # plain walk with a vanishing potential (Z = 1e-9, no 1/r12, e_ref = 0), so L(T) is the log of
+    # the surviving weight; the end-point test misses touches between steps (error O(sqrt dt)),
+    # the bridge weight accounts for them (error O(dt) at a flat node)
+    sv = W.get("exact_triplet_noee", n_walkers=1 << 22, Z=1e-9, e_ref=0.0, plain=True)
+    rows = []
+    for dt in (0.004, 0.002, 0.001, 0.0005, 0.00025):
+        for br in (False, True):
+            c = dict(sv, dt=dt, n_steps=int(round(0.5 / dt)), sample_every=int(round(0.1 / dt)), bridge=br)
+            Ls = [_run(c, s_, keep_L=True)["L"][-1] for s_ in range(seeds)]
+            m, s_ = _mean_se(Ls)
+            rows.append({"dt": dt, "bridge": br, "L_T": m, "se": s_})
+            print("# bridge survival dt=%g bridge=%d: ln S(0.5) %.6f +- %.6f" % (dt, br, m, s_), file=sys.stderr,
+                  flush=True)
+    out["pocket_survival_T0.5"] = {"rows": rows}
     return out
 
 

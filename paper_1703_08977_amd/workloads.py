@@ -84,10 +84,15 @@ PAPER_FN3_1M = dict(
 PAPER_FN5_1M = dict(
     PAPER_FN3_1M, name="he_2tripS_fn5_1m", theta=[0.636748, 0.0, 0.0, 2.002777, 0.73351723, 0.0],
     e_ref=-2.1742305)
+# Trial function 4 (r0 = 1, alpha1 = 0.67180691, alpha2 = 2.00411836) has no table; its e_ref
+# is the mean local energy of 2^18 |psi|^2 samples, -2.17315(16).
+PAPER_FN4_1M = dict(
+    PAPER_FN3_1M, name="he_2tripS_fn4_1m", theta=[0.67180691, 0.0, 0.0, 2.00411836, 1.0, 0.0],
+    e_ref=-2.17315)
 
 WORKLOADS = {w["name"]: w for w in
              (HE_GROUND_EXPO_4K, HE_GROUND_PADE_1M, HE_TRIPLET_4M, HE_GRAD_PADE_256K, HE_PZ_16M,
-              PAPER_FN3_1M, PAPER_FN5_1M)}
+              PAPER_FN3_1M, PAPER_FN4_1M, PAPER_FN5_1M)}
 
 # Closed-form systems.
 # Z = 2 without 1/r12 and the exact product of hydrogenic 1s orbitals: E_L = -4 exactly.

@@ -76,6 +76,7 @@ CASES = [
     ("hydrogen", dict()),
     ("he_1s_pade_1m", dict(dt=0.01, drift_limit=0.5, contract=2)),
     ("he_2tripS_fn3_1m", dict(precision="fp64")),
+    ("he_2tripS_fn4_1m", dict(precision="fp64")),
     ("he_2tripS_fn5_1m", dict(precision="fp64", noise="gauss", quad="trapezoid", dt=0.002)),
     # variants: plain Feynman-Kac walk, node-touch (bridge) weight
     ("he_1s_pade_1m", dict(dt=0.002, plain=True)),
@@ -156,8 +157,11 @@ def test_mixed_precision_variants_close_to_binary64(over):
     g = gpu_run(cfg, n_walkers=n, n_steps=400, sample_every=20)
     r = oracle.run(dict(cfg, precision="fp64"), np.arange(n), 400, 20)
     assert np.abs(g["x0"] - r["x0"]).max() <= 2.0**-23 * max(1.0, np.abs(r["x0"]).max())
+    # Brownian walkers of the plain walk reach the node often: compare the absorption
+    # decisions, then the weights of the walkers alive on both sides
+    assert (np.isfinite(g["lnw"]) == np.isfinite(r["lnw"])).mean() > 0.97
     both = np.isfinite(g["lnw"]) & np.isfinite(r["lnw"])
-    assert both.mean() > 0.9
+    assert both.mean() > 0.5
     assert np.median(np.abs(g["lnw"][both] - r["lnw"][both])) < 1e-4
     # the log space average stays within the binary32 rounding of the paths
     Lg, Lr = log_mean_weight(g["samples"]), log_mean_weight(r["samples"])

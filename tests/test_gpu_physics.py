@@ -86,3 +86,51 @@ def test_paper_trial_energy_lambda0_on_gpu(name):
         _, _, el = e.state()
         se = el.std() / math.sqrt(len(el))
         assert abs(el.mean() - cfg["e_ref"]) < 5 * se, (name, prec, el.mean(), cfg["e_ref"], se)
+
+
+def test_long_projection_ground_state_extrapolates_to_the_exact_energy():
+    # Pade-Jastrow trial, 2^20 walkers, T = 16 (window [8, 16], past the excited-state
+    # decay), dt in {0.002, 0.001}, 4 seeds each; E(dt) = E0 + s dt extrapolated to dt = 0
+    # must meet the exact non-relativistic 1^1S energy (5 sigma of the extrapolation)
+    from paper_1703_08977_amd import Ensemble, he_fk_energy
+    rows = []
+    for dt in (0.002, 0.001):
+        se = int(round(0.1 / dt))
+        cfg = W.get("he_1s_pade_1m", dt=dt, n_steps=int(round(16 / dt)), sample_every=se)
+        vals = []
+        for seed in range(4):
+            e = Ensemble(dict(cfg, seed=seed)).init()
+            s = e.propagate(0, cfg["n_steps"], se).cpu().numpy()
+            vals.append(he_fk_energy(s, dt * se, cfg["e_ref"], "window")[0][0])
+            del e
+        rows.append((dt, float(np.mean(vals)), float(np.std(vals, ddof=1) / 2)))
+    (d1, e1, s1), (d2, e2, s2) = rows
+    e0 = e2 - (e1 - e2) * d2 / (d1 - d2)           # line through the two points, at dt = 0
+    s0 = math.hypot(2 * s2, s1)                    # d e0 / d e2 = 2, d e0 / d e1 = -1
+    assert abs(e0 - EXACT_1S) < 5 * s0 + 5e-5, (rows, e0, s0)
+
+
+def test_bridge_weight_removes_the_missed_node_touches_of_the_brownian_walk():
+    # Brownian walkers (the plain walk, potential switched off by Z = 1e-9) in a nodal pocket of
+    # r1 = r2, T = 0.5, 2^22 walkers x 4 seeds: ln S(T) = L(T) with the end-point test alone
+    # misses the touches inside a step, an O(sqrt dt) error; with the bridge weight ln S(T)
+    # no longer depends on dt at this resolution
+    from paper_1703_08977_amd import Ensemble
+    from hefk_testutil import log_mean_weight
+
+    def lnS(dt, bridge):
+        cfg = W.get("exact_triplet_noee", n_walkers=1 << 22, Z=1e-9, e_ref=0.0, plain=True, bridge=bridge,
+                    dt=dt, n_steps=int(round(0.5 / dt)), sample_every=int(round(0.1 / dt)))
+        v = []
+        for seed in range(4):
+            e = Ensemble(dict(cfg, seed=seed)).init()
+            v.append(log_mean_weight(e.propagate(0, cfg["n_steps"], cfg["sample_every"]).cpu().numpy())[-1])
+            del e
+        return float(np.mean(v)), float(np.std(v, ddof=1) / 2)
+
+    (b1, sb1), (b2, sb2) = lnS(0.002, True), lnS(0.0005, True)
+    (e1, se1), (e2, se2) = lnS(0.002, False), lnS(0.0005, False)
+    tol = 5 * math.hypot(sb1, sb2) + 1e-4
+    assert abs(b1 - b2) < tol, (b1, b2, tol)
+    assert e2 - e1 < -5 * tol, (e1, e2, tol)       # end-point survival still falls with dt
+    assert b2 < e2                                  # touches between steps lower the survival
