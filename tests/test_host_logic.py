@@ -258,3 +258,17 @@ def test_binary64_step_functions_against_the_c_library():
     assert err["log"] <= 2.5 and err["exp"] <= 1.5 and err["sqrt"] <= 1.0 and err["rcp"] <= 1.0, err
     assert err["sin"] <= 2.0 and err["cos"] <= 2.0, err   # absolute, in units of 2^-53
     assert out[1].split()[1:] == ["-inf", "0", "inf", "0"]
+
+
+def test_bench_reports_committed_traffic_only_for_the_profiled_configuration():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    assert len(bench.source_digest()) == 64
+    # another workload, or the same one at another precision, never inherits the profiled bytes
+    assert bench.committed_traffic(W.get("he_2P_pz_16m", precision="fp64")) is None
+    assert bench.committed_traffic(W.get("he_2tripS_4m")) is None
+    t = bench.committed_traffic(W.get("he_2P_pz_16m"))
+    assert t is None or 1e9 < t < 1e10
