@@ -146,10 +146,13 @@ HD void sincos2pi(double u, double* s_out, double* c_out)
     pc = ::fma(pc, z, 1.0 / 24.0);               // + 1/4!
     pc = ::fma(pc, z, -0.5);                     // - 1/2!
     const double cs = ::fma(z, pc, 1.0);
-    // angle = k pi/2 + t
+    // angle = k pi/2 + t: odd quadrants exchange sin and cos; sin is negated in
+    // quadrants 2, 3 and cos in quadrants 1, 2 (selects, no branches)
     const int q = ((int)k) & 3;
-    *s_out = (q == 0) ? sn : (q == 1) ? cs : (q == 2) ? -sn : -cs;
-    *c_out = (q == 0) ? cs : (q == 1) ? -sn : (q == 2) ? -cs : sn;
+    const double a = (q & 1) ? cs : sn;
+    const double b = (q & 1) ? sn : cs;
+    *s_out = (q & 2) ? -a : a;
+    *c_out = ((q + 1) & 2) ? -b : b;
 }
 
 // e^x for x <= 0 (and moderate x > 0)
