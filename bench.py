@@ -148,8 +148,19 @@ def cpu_baseline(cfg, n_walkers):
     ws = n_walkers * cfg["n_steps"]
     return {"value": ws / (t2 - t0), "unit": "walker-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "walker ids 0..%d of the workload, all %d steps, start ensemble included "
-                      "(start %.2f s, propagation %.2f s, propagation-only %.4g walker-steps/s)" %
-                      (n_walkers - 1, cfg["n_steps"], t1 - t0, t2 - t1, ws / (t2 - t1))}
+                      "(start %.2f s, propagation %.2f s, propagation-only %.4g walker-steps/s); host CPU: %s" %
+                      (n_walkers - 1, cfg["n_steps"], t1 - t0, t2 - t1, ws / (t2 - t1), cpu_model())}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():

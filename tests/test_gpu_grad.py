@@ -109,6 +109,29 @@ def test_autograd_function_uses_the_adjoint():
                                            log_mean_weight(s.cpu().numpy())[-2]) / dts)) < 1e-12
 
 
+def test_grad_vanishes_in_expectation_for_the_exact_trial():
+    # Z = 2 without 1/r12 and psi = e^{-alpha (r1 + r2)} at alpha = 2: E_L = -4 everywhere, so
+    # w = 1 on every path and dE(T)/d alpha is the mean of 1/r1 + 1/r2 - 4 over the last
+    # interval, zero under |psi|^2 (<1/r> = alpha); the beta component is exactly zero
+    from paper_1703_08977_amd import _lib
+    cfg = W.get("he_1s_pade_grad_256k", trial="expo", theta=[2.0], ee=0, e_ref=-4.0, dt=0.0005,
+                n_steps=1000, sample_every=50, ckpt_every=50)
+    dts = cfg["dt"] * cfg["sample_every"]
+    ns = cfg["n_steps"] // cfg["sample_every"] + 1
+    gL = np.zeros(ns)
+    gL[-1], gL[-2] = -1.0 / dts, 1.0 / dts
+    g = []
+    for seed in range(4):
+        c = dict(cfg, seed=seed)
+        e, ckpt, s, _ = _forward(c)
+        assert np.all(log_mean_weight(s.cpu().numpy()) == 0.0)
+        g.append(_grad(e, ckpt, s, c, gL, flags=_lib.GRAD_SCORE))
+    g = np.array(g)
+    assert np.all(g[:, 1] == 0.0)
+    # per seed: sigma(1/r1 + 1/r2) / sqrt(N) = sqrt(2 alpha^2 / N) = 0.0055
+    assert abs(g[:, 0].mean()) < 5 * 0.0055 / 2, g[:, 0]
+
+
 def test_grad_rejects_unsupported_cases():
     import torch
     from paper_1703_08977_amd import _lib, api

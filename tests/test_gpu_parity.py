@@ -249,6 +249,13 @@ def test_full_size_pz_fp64():
     _last_row_property(g)
 
 
+def test_full_size_triplet_fp64():
+    cfg, g, r, ids = _full_size("he_2tripS_4m", precision="fp64")
+    gg = {k: g[k][ids] for k in ("x0", "x", "lnw")}
+    _compare(gg, r, node=True)
+    _last_row_property(g)
+
+
 def test_full_size_pz_mixed_last_row():
     cfg = W.get("he_2P_pz_16m")
     g = gpu_run(cfg)

@@ -88,15 +88,17 @@ def test_paper_trial_energy_lambda0_on_gpu(name):
         assert abs(el.mean() - cfg["e_ref"]) < 5 * se, (name, prec, el.mean(), cfg["e_ref"], se)
 
 
-def test_long_projection_ground_state_extrapolates_to_the_exact_energy():
+@pytest.mark.parametrize("noise", ["gauss", "pm1"])
+def test_long_projection_ground_state_extrapolates_to_the_exact_energy(noise):
     # Pade-Jastrow trial, 2^20 walkers, T = 16 (window [8, 16], past the excited-state
     # decay), dt in {0.002, 0.001}, 4 seeds each; E(dt) = E0 + s dt extrapolated to dt = 0
-    # must meet the exact non-relativistic 1^1S energy (5 sigma of the extrapolation)
+    # must meet the exact non-relativistic 1^1S energy (5 sigma of the extrapolation), for
+    # Gaussian increments and for the paper's +-1 walk alike (both are weak order 1)
     from paper_1703_08977_amd import Ensemble, he_fk_energy
     rows = []
     for dt in (0.002, 0.001):
         se = int(round(0.1 / dt))
-        cfg = W.get("he_1s_pade_1m", dt=dt, n_steps=int(round(16 / dt)), sample_every=se)
+        cfg = W.get("he_1s_pade_1m", dt=dt, n_steps=int(round(16 / dt)), sample_every=se, noise=noise)
         vals = []
         for seed in range(4):
             e = Ensemble(dict(cfg, seed=seed)).init()
