@@ -34,6 +34,8 @@ struct has_node {
 // ---------------------------------------------------------------------------
 namespace m {
 
+HD double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+HD float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 HD double sqrt_(double x) { return f64::sqrt(x); }
 HD double rcp_(double x) { return f64::rcp(x); }
 HD double exp_(double x) { return f64::exp(x); }
@@ -165,7 +167,7 @@ HD float unit32(uint32_t w, float)
 template <typename R>
 HD R unit21(uint32_t f)
 {
-    return ((R)f + (R)0.5) * (R)0x1p-21;
+    return m::fma_((R)f, (R)0x1p-21, (R)0x1p-22);  // (f + 1/2) 2^-21 with one rounding of an exact value
 }
 
 template <typename R>
