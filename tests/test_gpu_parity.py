@@ -261,3 +261,62 @@ def test_full_size_pz_mixed_last_row():
     g = gpu_run(cfg)
     _last_row_property(g)
     assert g["samples"][-1, 5] == 0
+
+
+# --------------------------------------------------------------------------
+# Edge cases: walker ids across the 32-bit boundary of the counter, a call
+# with no steps, and an ensemble whose arrays exceed 2^31 elements.
+# --------------------------------------------------------------------------
+
+def test_walker_ids_across_the_32bit_counter_boundary():
+    # the global id fills counter words 2 (low) and 3 (high): ids 2^32 - 150 .. 2^32 + 150
+    cfg = W.get("he_1s_pade_1m", dt=0.002)
+    off, n = (1 << 32) - 150, 301
+    g = gpu_run(cfg, n_walkers=n, n_steps=100, sample_every=20, walker_offset=off)
+    r = oracle.run(cfg, off + np.arange(n, dtype=np.uint64), 100, 20)
+    _compare(g, r)
+    assert rel_err(log_mean_weight(g["samples"]), log_mean_weight(r["samples"])).max() < TOL
+
+
+def test_propagate_without_steps_returns_the_entry_row():
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    cfg = W.get("he_2tripS_4m", precision="fp64")
+    e = Ensemble(cfg, n_walkers=1000).init()
+    x0, lnw0, _ = e.state()
+    s = e.propagate(0, 0, 1).cpu().numpy()
+    torch.cuda.synchronize()
+    x1, lnw1, _ = e.state()
+    assert s.shape == (1, 8) and np.array_equal(x0, x1) and np.array_equal(lnw0, lnw1)
+    r = oracle.run(cfg, np.arange(1000), 0, 1)
+    assert np.array_equal(s[0, 4:7], r["samples"][0, 4:7])
+    assert abs(log_mean_weight(s)[0]) == 0.0
+
+
+def test_ensemble_beyond_2_31_array_elements():
+    # 2^29 + 37 walkers in binary64 (34 GB of state): the x rows reach element 5 N > 2^31;
+    # 20 steps, sampled walkers against the oracle, the sample row against the final ln w
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    n = (1 << 29) + 37
+    cfg = W.get("he_1s_pade_1m", dt=0.002, n_walkers=n, n_steps=20, sample_every=20)
+    e = Ensemble(cfg).init()
+    rng = np.random.default_rng(29)
+    ids = np.unique(np.concatenate([[0, 1, n // 6, (1 << 31) // 6 + 1, n - 2, n - 1],
+                                    rng.integers(0, n, 42)]))
+    it = torch.from_numpy(ids).cuda()
+    x0 = e.x[:, it].double().t().cpu().numpy()
+    s = e.propagate(0, 20, 20).cpu().numpy()
+    torch.cuda.synchronize()
+    x = e.x[:, it].double().t().cpu().numpy()
+    lnw = e.lnw.cpu().numpy()
+    r = oracle.run(cfg, ids.astype(np.uint64), 20, 20)
+    assert rel_err(x0, r["x0"]).max() < TOL
+    assert rel_err(x, r["x"]).max() < TOL
+    assert rel_err(lnw[ids], r["lnw"]).max() < TOL
+    assert s[-1, 6] == n and s[-1, 4] == n
+    m = lnw.max()
+    L = m + np.log(np.sum(np.exp(lnw - m))) - np.log(n)
+    assert abs(L - log_mean_weight(s)[-1]) < 1e-12
+    del e
+    torch.cuda.empty_cache()
