@@ -238,26 +238,32 @@ def dlnpsi_dtheta(cfg, y0, direction):
     return np.array([lib().ofk_dlnpsi_dtheta(ctypes.byref(p), _ptr(y0[i]), direction) for i in range(len(y0))])
 
 
-def grad_objective(cfg, ids, y0, n_steps, sample_every, gL, score=False):
-    """d/d(alpha, beta) of J = sum_s gL_s L_s, L_s = ln( (1/N) sum_i w_is ), at fixed Y0 and noise.
+def grad_objective(cfg, ids, y0, n_steps, sample_every, gL, score=False, gL2=None):
+    """d/d(alpha, beta) of J = sum_s gL_s L_s + sum_s gL2_s L2_s at fixed Y0 and noise, with
+    L_s = ln( (1/N) sum_i w_is ) and L2_s = ln( (1/N) sum_i w_is^2 ).
 
-    dL_s/dtheta = sum_i p_is d l_is / dtheta, p_is = w_is / sum_i w_is.  With
-    ``score`` the derivative of the |psi|^2 start law is added through the
-    score 2 d ln|psi(Y0)|/dtheta: sum_i (p_is - 1/N) s_i per sample.
+    dL_s/dtheta = sum_i p_is d l_is / dtheta, p_is = w_is / sum_i w_is, and
+    dL2_s/dtheta = sum_i q_is 2 d l_is / dtheta, q_is = w_is^2 / sum_i w_is^2.  With
+    ``score`` the derivative of the |psi|^2 start law is added through the score
+    s_i = 2 d ln|psi(Y0_i)|/dtheta: sum_i (p_is - 1/N) s_i for L_s and sum_i (q_is - 1/N) s_i
+    for L2_s (each a derivative of a log of an average over the start law).
     """
     ids = _ids(ids)
     x, lnw, el, ell, els = propagate(cfg, ids, y0, np.zeros(len(y0)), 0, n_steps, sample_every)
     m = ell.max(axis=0)
     w = np.exp(ell - m)
     p = w / w.sum(axis=0)
+    q = w * w / (w * w).sum(axis=0)
     g = np.zeros(2)
     gL = np.asarray(gL, dtype=np.float64)
+    gL2 = np.zeros_like(gL) if gL2 is None else np.asarray(gL2, dtype=np.float64)
     for d in range(2):
         dl = dlnw_dtheta(cfg, ids, y0, n_steps, sample_every, d)
-        g[d] = float(np.sum(gL * np.sum(p * dl, axis=0)))
+        g[d] = float(np.sum(gL * np.sum(p * dl, axis=0)) + np.sum(gL2 * np.sum(q * 2.0 * dl, axis=0)))
         if score:
             s = 2.0 * dlnpsi_dtheta(cfg, y0, d)
             g[d] += float(np.sum(gL * ((p - 1.0 / len(ids)) * s[:, None]).sum(axis=0)))
+            g[d] += float(np.sum(gL2 * ((q - 1.0 / len(ids)) * s[:, None]).sum(axis=0)))
     return g
 
 

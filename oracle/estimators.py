@@ -25,6 +25,13 @@ def log_mean_weight(samples):
     return s[:, 0] + np.log(s[:, 1]) - np.log(s[:, 6])
 
 
+def log_mean_square_weight(samples):
+    """ln((1/N) sum w^2) from the rows: 2 m + ln S2 - ln N.  With L it gives the relative
+    variance of the weights, ln(<w^2> / <w>^2) = L2 - 2 L, i.e. -ln(ESS / N)."""
+    s = np.asarray(samples, dtype=np.float64)
+    return 2.0 * s[:, 0] + np.log(s[:, 3]) - np.log(s[:, 6])
+
+
 def e_fd(samples, dt_sample, e_ref):
     L = log_mean_weight(samples)
     return e_ref - np.diff(L) / dt_sample

@@ -435,12 +435,14 @@ def test_complex_step_gradient_vs_central_differences():
     y0, _ = oracle.init(cfg, ids)
     ns = 200 // 50 + 1
     gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
-    g = oracle.grad_objective(cfg, ids, y0, 200, 50, gL)
+    gL2 = np.array([0.0, -0.2, 0.4, 0.0, 0.9])  # weights on ln <w^2>
+    g = oracle.grad_objective(cfg, ids, y0, 200, 50, gL, gL2=gL2)
 
     def J(theta):
         c = dict(cfg, theta=theta)
         _, _, _, ell, els = oracle.propagate(c, ids, y0, np.zeros(len(ids)), 0, 200, 50)
-        return float(np.sum(gL * est.log_mean_weight(oracle.tuples(ell, els))))
+        rows = oracle.tuples(ell, els)
+        return float(np.sum(gL * est.log_mean_weight(rows)) + np.sum(gL2 * est.log_mean_square_weight(rows)))
 
     th = list(cfg["theta"])
     for d, h in ((0, 1e-5), (1, 1e-5)):
@@ -450,6 +452,14 @@ def test_complex_step_gradient_vs_central_differences():
         fd = (J(tp) - J(tm)) / (2 * h)
         assert abs(g[d] - fd) < 1e-6 * max(1.0, abs(fd)), (d, g[d], fd)
     assert ns == 5
+
+
+def test_second_moment_of_the_weights_from_the_rows():
+    # ln <w^2> from (m, S2, N) of the tuple rows equals the direct log of the mean square weight
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=100, sample_every=50)
+    r = oracle.run(cfg, np.arange(300), 100, 50)
+    direct = np.log(np.mean(np.exp(2.0 * r["ell"]), axis=0))
+    assert np.abs(est.log_mean_square_weight(r["samples"]) - direct).max() < 1e-13
 
 
 def test_score_term_of_start_law():
