@@ -221,13 +221,17 @@ int he_fk_energy(const double* samples, int64_t n_samples, double dt_sample, dou
 
 /* ---- pathwise gradient (adjoint) ---- */
 #define HE_FK_GRAD_SCORE 1 /* add the derivative of the |psi_T|^2 start law (score term) */
+#define HE_FK_GRAD_MOMENT2 2 /* gL holds 2 n_samples weights: on L_s, then on L2_s = ln <w^2>_s */
 
 /* Bytes of device scratch he_fk_grad needs; 0 on invalid arguments. */
 size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_steps, int32_t sample_every,
                                 int32_t ckpt_every);
 
 /*
- * he_fk_grad: d/d(theta0, theta1) = d/d(alpha, beta) of J = sum_s gL[s] L_s,
+ * he_fk_grad: d/d(theta0, theta1) = d/d(alpha, beta) of J = sum_s gL[s] L_s
+ * (+ sum_s gL[n_samples + s] L2_s with HE_FK_GRAD_MOMENT2, L2_s = 2 m + ln S2 - ln N,
+ * the log of the mean square weight: L2 - 2 L is the log relative variance of the
+ * weights, -ln(ESS / N), the objective for tuning psi_T to cut the estimator's variance),
  * L_s the log space average of sample row s of one he_fk_propagate call from
  * step 0 with checkpoints, for the nodeless trials (EXPO, PADE), FP64, no
  * drift limiting.  The derivative is pathwise: start positions (checkpoint
@@ -240,9 +244,10 @@ size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_steps, int32_t 
  * A_j the weight of step j's local energy in J).
  *   ckpt    : device, the checkpoints [n_steps/ckpt_every + 1][7][N] of that call;
  *   samples : device, its sample rows (m and S0 give each walker's share of L_s);
- *   gL      : HOST, [n_steps / sample_every + 1];
- *   flags   : 0 or HE_FK_GRAD_SCORE (adds sum_s gL[s] sum_i (p_is - 1/N) 2 d ln|psi(Y0_i)|/d theta,
- *             the derivative through the |psi|^2 law of the start positions);
+ *   gL      : HOST, [n_steps / sample_every + 1], or twice that with HE_FK_GRAD_MOMENT2;
+ *   flags   : an OR of HE_FK_GRAD_SCORE (adds sum_s gL[s] sum_i (p_is - 1/N) 2 d ln|psi(Y0_i)|/d theta,
+ *             the derivative through the |psi|^2 law of the start positions; for L2_s the shares
+ *             are q_is = w_is^2 / sum_i w_is^2) and HE_FK_GRAD_MOMENT2;
  *   scratch : device, at least he_fk_grad_scratch_bytes(...) bytes;
  *   dtheta  : device, [2] binary64 output (written by the last kernel of the call).
  * Constraints: n_steps % sample_every == 0, n_steps % ckpt_every == 0, and one of

@@ -28,6 +28,7 @@ NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}
 E_METHOD = {"fd": 0, "window": 1, "fit": 2, "mixed": 3}
 GRAD_SCORE = 1
+GRAD_MOMENT2 = 2  # gL carries a second block of weights, on L2_s = ln <w^2>_s
 FLAG_PLAIN = 1   # plain Feynman-Kac walk: no drift, integrand V - e_ref
 FLAG_BRIDGE = 2  # node-touch (Brownian bridge) survival weight per step (node trials)
 

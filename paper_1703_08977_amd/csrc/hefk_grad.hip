@@ -1,5 +1,6 @@
 // hefk_grad.hip -- pathwise (fixed start, fixed noise) gradient of
-// J = sum_s gL_s L_s with respect to the trial parameters (alpha, beta):
+// J = sum_s gL_s L_s (+ sum_s gL2_s L2_s, L2 = ln <w^2>) with respect to the
+// trial parameters (alpha, beta):
 // one thread per walker walks the checkpoint segments backwards, recomputes
 // each segment from its checkpoint into a scratch tape (noise regenerated
 // from Philox), and runs the adjoint recursion of hefk_adjoint.hpp over it.
@@ -32,7 +33,8 @@ struct GArgs {
     int32_t n_steps, sample_every, ckpt_every, score;
     const double* ckpt;     // [n_ckpt][7][n]
     const double* samples;  // [n_samples][8]
-    const double* g;        // [n_samples]
+    const double* g;        // [n_samples] weights on L_s
+    const double* g2;       // [n_samples] weights on L2_s, or null
     double* tape;           // [ckpt_every + 1][7][n]
     double* partial;        // [gridDim.x][2]
     double inv_n_total, g_sum;
@@ -69,9 +71,12 @@ struct DeviceTape {
 struct SampleView {
     const double* rows;
     const double* g;
+    const double* g2;
     __device__ double m(int s) const { return rows[8 * s]; }
     __device__ double s0(int s) const { return rows[8 * s + 1]; }
+    __device__ double s2(int s) const { return rows[8 * s + 3]; }
     __device__ double gs(int s) const { return g[s]; }
+    __device__ double g2s(int s) const { return g2 ? g2[s] : 0.0; }
 };
 
 template <int TRIAL, int NOISE>
@@ -88,15 +93,16 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(const GArgs a)
         st.g0 = (uint32_t)gid;
         st.g1 = (uint32_t)(gid >> 32);
         DeviceTape tape{a.ckpt, a.tape, a.n, i};
-        SampleView sv{a.samples, a.g};
-        double P = 0.0;
+        SampleView sv{a.samples, a.g, a.g2};
+        double P = 0.0, Q = 0.0;
         walker_reverse<TRIAL, NOISE>(a.tp, a.sc, a.dt, a.sqdt, st, a.n_steps, a.sample_every, a.ckpt_every, sv,
-                                     tape, gth, &P);
+                                     tape, gth, &P, &Q);
         if (a.score) {
             double y0[6], l0, sc[2];
             tape.load_ckpt(0, y0, l0);
             dlnpsi_dtheta<TRIAL>(a.tp, y0, sc);
-            const double wgt = P - a.g_sum * a.inv_n_total;
+            // start-law weight: sum_s (g_s p_is + g2_s q_is) - (sum_s g_s + g2_s) / N
+            const double wgt = (P - Q) - a.g_sum * a.inv_n_total;
             gth[0] += 2.0 * sc[0] * wgt;
             gth[1] += 2.0 * sc[1] * wgt;
         }
@@ -178,7 +184,7 @@ int layout(const he_fk_params* p, int64_t n_steps, int32_t sample_every, int32_t
     L->tape = 0;
     L->partial = up256((size_t)(ckpt_every + 1) * 7 * (size_t)n * sizeof(double));
     L->g = L->partial + up256((size_t)L->blocks * 2 * sizeof(double));
-    L->total = L->g + up256((size_t)(n_steps / sample_every + 1) * sizeof(double));
+    L->total = L->g + up256((size_t)2 * (n_steps / sample_every + 1) * sizeof(double));
     return HE_FK_OK;
 }
 
@@ -203,11 +209,12 @@ extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const doubl
     int rc = layout(p, n_steps, sample_every, ckpt_every, &L);
     if (rc) return rc;
     if (!ckpt || !samples || !gL || !scratch || !dtheta) return HE_FK_EINVAL;
-    if (flags & ~HE_FK_GRAD_SCORE) return HE_FK_EINVAL;
+    if (flags & ~(HE_FK_GRAD_SCORE | HE_FK_GRAD_MOMENT2)) return HE_FK_EINVAL;
     if (scratch_bytes < L.total) return HE_FK_ESCRATCH;
     const int64_t n_samples = n_steps / sample_every + 1;
+    const int64_t n_g = (flags & HE_FK_GRAD_MOMENT2) ? 2 * n_samples : n_samples;
     double g_sum = 0.0;
-    for (int64_t s = 0; s < n_samples; ++s) {
+    for (int64_t s = 0; s < n_g; ++s) {
         if (!std::isfinite(gL[s])) return HE_FK_EINVAL;
         g_sum += gL[s];
     }
@@ -242,11 +249,12 @@ extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const doubl
     a.tape = (double*)(base + L.tape);
     a.partial = (double*)(base + L.partial);
     a.g = (double*)(base + L.g);
+    a.g2 = (flags & HE_FK_GRAD_MOMENT2) ? a.g + n_samples : nullptr;
     a.g_sum = g_sum;
     // 1/N of the space average: every walker of the propagate call counts (n_total of row 0)
     a.inv_n_total = 1.0 / (double)p->n_walkers;
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync((void*)a.g, gL, (size_t)n_samples * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync((void*)a.g, gL, (size_t)n_g * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return HE_FK_EDEVICE;
     const int nk = p->noise == HE_FK_NOISE_PM1 ? NOISE_PM1 : (p->contract == 2 ? NOISE_G2 : NOISE_G1);
     hipLaunchKernelGGL(pick(p->trial, nk), dim3((unsigned)L.blocks), dim3(kGradBlock), 0, s, a);

@@ -11,12 +11,12 @@ namespace hefk {
 template <int TRIAL, int NOISE, class Samples, class Tape>
 HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, double dt, double sqdt, const Stream& st,
                        int n_steps, int sample_every, int ckpt_every, const Samples& sv, Tape& tape, double gth[2],
-                       double* p_total)
+                       double* p_total, double* q_total)
 {
     const bool right = sc.quad_right != 0;
     const int n_seg = n_steps / ckpt_every;
     double lam[6] = {0, 0, 0, 0, 0, 0};
-    double P = 0.0;
+    double P = 0.0, Q = 0.0;
     for (int seg = n_seg - 1; seg >= 0; --seg) {
         const int k0 = seg * ckpt_every;
         // recompute the segment from its checkpoint (same arithmetic as the forward kernel)
@@ -38,8 +38,17 @@ HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, doubl
             tape.get(j - k0, y, lnw);
             double H = 0.0;
             if (j % sample_every == 0) {
+                // dJ/d ln w_j: g_s p_is + 2 g2_s q_is, with the walker's shares
+                // p_is = w / sum w of L_s and q_is = w^2 / sum w^2 of L2_s
                 const int s = j / sample_every;
-                H = sv.gs(s) * ::exp(lnw - sv.m(s)) / sv.s0(s);
+                const double e = ::exp(lnw - sv.m(s));
+                H = sv.gs(s) * e / sv.s0(s);
+                const double g2 = sv.g2s(s);
+                if (g2 != 0.0) {
+                    const double q = g2 * (e * e) / sv.s2(s);
+                    H += 2.0 * q;
+                    Q += q;
+                }
             }
             const double A = adjoint_weight(j, P, H, dt, right);
             double V[6], gy[6], gt[2];
@@ -53,7 +62,8 @@ HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, doubl
             P += H;
         }
     }
-    *p_total = P;
+    *p_total = P;  // sum_s (g_s p_is + 2 g2_s q_is)
+    *q_total = Q;  // sum_s g2_s q_is
 }
 
 }  // namespace hefk

@@ -7,7 +7,9 @@ c2  1^1S, Pade-Jastrow, 2^20 walkers, T = 5, dt in {0.002, 0.001, 0.0005}: windo
     per dt over seeds, and its linear extrapolation dt -> 0.
 c3  2^3S triplet (exact node), 2^22 walkers, dt = 0.001, T = 4: mixed vs FP64 on the same
     seeds (paired difference), absorbed fraction.
-c4  gradient descent of E(T = 2) over (alpha, beta), 2^18 walkers, adjoint gradient.
+c4  tuning of (alpha, beta) by 20 adjoint-gradient steps, 2^18 walkers: sigma^2(E_L) (one-step
+    weight variance), the weight variance at T = 2 and E(T = 2) as objectives; the estimator
+    spread, ESS and sigma(E_L) before and after.
 c5  P_z (2^1P) "+", 2^24 walkers, dt = 0.0005, T = 6: mixed vs FP64, paired difference,
     seed-to-seed errors and the time to a 1e-5 Ha statistical error.
 paper  the setting of Tables 1 and 2: trial functions 3 and 5, the +-1 walk at scale 30
@@ -143,23 +145,47 @@ def c5(seeds=16):
     return r
 
 
-def c4(seeds=1):
+def c4(seeds=32, first_step=0.02):
+    """Tuning of the Pade-Jastrow trial with the adjoint (score term included), 20 gradient steps
+    at a fixed seed, for three objectives:
+      el_variance      ln(<w^2>/<w>^2)/dt^2 after one step: sigma^2(E_L) under |psi|^2 to
+                       leading order in dt (the variational variance criterion);
+      weight_variance  ln(<w^2>/<w>^2) at T = 2: the weight spread, i.e. -ln(ESS/N);
+      energy           E(T = 2), which at finite dt rewards the time-step bias.
+    For each end point: the estimator's seed-to-seed spread of E(T), the ESS at T and sigma(E_L)
+    of the start ensemble, on fresh seeds."""
     from . import workloads as W
+    from . import Ensemble, he_fk_energy
     from .autograd import descend
     cfg = W.get("he_1s_pade_grad_256k")
-    t0 = time.perf_counter()
-    trace = descend(cfg, score=True, log=lambda r: print("# c4 %s" % json.dumps(r), file=sys.stderr, flush=True))
-    wall = time.perf_counter() - t0
-    # spread of E(T) over seeds before and after, at fixed parameters
+    runs = {}
+    for obj, kw in (("el_variance", {"first_step": first_step}), ("weight_variance", {"first_step": first_step}),
+                    ("energy", {"lr": 1.0})):
+        t0 = time.perf_counter()
+        tr = descend(cfg, objective=obj, log=lambda r: print("# c4 %s" % json.dumps(r), file=sys.stderr,
+                                                              flush=True), **kw)
+        runs[obj] = {"trace": tr, "wall_s": time.perf_counter() - t0}
+
     def spread(theta):
         c = dict(cfg, theta=[theta[0], theta[1], cfg["theta"][2], 0.0])
-        vals = [_run(c, s)["E_fd_last"] for s in range(8)]
-        return _mean_se(vals) + (float(np.std(vals, ddof=1)),)
-    before = spread(cfg["theta"][:2])
-    after = spread([trace[-1]["alpha"], trace[-1]["beta"]])
-    return {"workload": cfg["name"], "trace": trace, "wall_s": wall,
-            "E_T_before": {"mean": before[0], "se": before[1], "sigma": before[2]},
-            "E_T_after": {"mean": after[0], "se": after[1], "sigma": after[2]}}
+        E, ess, sig = [], [], []
+        for s_ in range(100, 100 + seeds):
+            e = Ensemble(dict(c, seed=s_)).init()
+            _, _, el = e.state()
+            sig.append(float(el.std()))
+            h = e.propagate(0, c["n_steps"], c["sample_every"]).cpu().numpy()
+            E.append(float(he_fk_energy(h, c["dt"] * c["sample_every"], c["e_ref"], "fd")[0][-1]))
+            ess.append(float(h[-1, 1] ** 2 / h[-1, 3] / h[-1, 6]))
+            del e
+        m, se = _mean_se(E)
+        return {"theta": [float(theta[0]), float(theta[1])], "E_T_mean": m, "E_T_se": se,
+                "E_T_seed_sigma": float(np.std(E, ddof=1)), "ess_fraction_T": float(np.mean(ess)),
+                "sigma_EL_start": float(np.mean(sig))}
+    out = {"workload": cfg["name"], "first_step": first_step, "before": spread(cfg["theta"][:2])}
+    for obj, r in runs.items():
+        out[obj] = {"trace": r["trace"], "wall_s": r["wall_s"],
+                    "after": spread([r["trace"][-1]["alpha"], r["trace"][-1]["beta"]])}
+    return out
 
 
 def paper(seeds=8):

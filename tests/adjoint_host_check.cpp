@@ -3,9 +3,9 @@
 //
 // stdin line 1: trial ee quad contract n_met Z t0 t1 t2 t3 dt e_ref metropolis_sigma init_sigma seed
 //               n_steps sample_every ckpt_every
-// line 2: n_samples, then n_samples triples (m_s S0_s g_s)
+// line 2: n_samples, then n_samples quintuples (m_s S0_s S2_s g_s g2_s)
 // line 3: n id_0 ... id_{n-1}
-// stdout per walker: dJ/dalpha dJ/dbeta P (P = sum_s g_s p_{i,s})
+// stdout per walker: dJ/dalpha dJ/dbeta P Q (P = sum_s g_s p_is + 2 g2_s q_is, Q = sum_s g2_s q_is)
 #include <cstdio>
 #include <vector>
 
@@ -33,10 +33,12 @@ struct HostTape {
 };
 
 struct HostSamples {
-    std::vector<double> m_, s0_, g_;
+    std::vector<double> m_, s0_, s2_, g_, g2_;
     double m(int s) const { return m_[s]; }
     double s0(int s) const { return s0_[s]; }
+    double s2(int s) const { return s2_[s]; }
     double gs(int s) const { return g_[s]; }
+    double g2s(int s) const { return g2_[s]; }
 };
 
 template <int TRIAL, int NOISE>
@@ -68,9 +70,9 @@ void one(const TrialParams<double>& tp, const StepConst& sc, int n_met, double m
         walker_step<double, TRIAL>(tp, sc, dt, sq, xi, w);
         if ((k + 1) % ce == 0) save((k + 1) / ce);
     }
-    double gth[2] = {0, 0}, P = 0;
-    walker_reverse<TRIAL, NOISE>(tp, sc, dt, sq, st, n_steps, se, ce, hs, tape, gth, &P);
-    std::printf("%.17g %.17g %.17g\n", gth[0], gth[1], P);
+    double gth[2] = {0, 0}, P = 0, Q = 0;
+    walker_reverse<TRIAL, NOISE>(tp, sc, dt, sq, st, n_steps, se, ce, hs, tape, gth, &P, &Q);
+    std::printf("%.17g %.17g %.17g %.17g\n", gth[0], gth[1], P, Q);
 }
 
 int main()
@@ -86,11 +88,13 @@ int main()
     if (std::scanf("%d", &ns) != 1) return 2;
     HostSamples hs;
     for (int s = 0; s < ns; ++s) {
-        double a, b, c;
-        if (std::scanf("%lf %lf %lf", &a, &b, &c) != 3) return 2;
+        double a, b, c, d, e;
+        if (std::scanf("%lf %lf %lf %lf %lf", &a, &b, &c, &d, &e) != 5) return 2;
         hs.m_.push_back(a);
         hs.s0_.push_back(b);
-        hs.g_.push_back(c);
+        hs.s2_.push_back(c);
+        hs.g_.push_back(d);
+        hs.g2_.push_back(e);
     }
     TrialParams<double> tp{th[0], th[1], th[2], th[3], Z, (double)ee, 1.0, 0.0};
     StepConst sc{dt, 0.5 * dt, e_ref, quad, 0.0};

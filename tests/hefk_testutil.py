@@ -112,8 +112,9 @@ def adjoint_harness():
     return _ADJ
 
 
-def adjoint_host_run(cfg, ids, n_steps, sample_every, ckpt_every, samples, g):
-    """Per-walker (dJ/dalpha, dJ/dbeta, P) from the host build of the reverse sweep."""
+def adjoint_host_run(cfg, ids, n_steps, sample_every, ckpt_every, samples, g, g2=None):
+    """Per-walker (dJ/dalpha, dJ/dbeta, P, Q) from the host build of the reverse sweep."""
+    g2 = np.zeros(len(samples)) if g2 is None else g2
     import oracle
     th = [float(v) for v in (list(cfg["theta"]) + [0.0] * 4)[:4]]
     line = "%d %d %d %d %d %r %r %r %r %r %r %r %r %r %d %d %d %d" % (
@@ -121,7 +122,8 @@ def adjoint_host_run(cfg, ids, n_steps, sample_every, ckpt_every, samples, g):
         cfg["n_metropolis"], float(cfg["Z"]), *th, float(cfg["dt"]), float(cfg["e_ref"]),
         float(cfg["metropolis_sigma"]), float(cfg["init_sigma"]), int(cfg["seed"]), n_steps, sample_every,
         ckpt_every)
-    l2 = "%d " % len(samples) + " ".join("%r %r %r" % (float(samples[s, 0]), float(samples[s, 1]), float(g[s]))
+    l2 = "%d " % len(samples) + " ".join("%r %r %r %r %r" % (float(samples[s, 0]), float(samples[s, 1]),
+                                                            float(samples[s, 3]), float(g[s]), float(g2[s]))
                                          for s in range(len(samples)))
     inp = line + "\n" + l2 + "\n%d %s\n" % (len(ids), " ".join(str(int(i)) for i in ids))
     out = subprocess.run([adjoint_harness()], input=inp, capture_output=True, text=True, check=True).stdout

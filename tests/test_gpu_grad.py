@@ -67,6 +67,47 @@ def test_grad_score_term_matches_oracle():
     assert np.abs(got - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-3), (got, ref)
 
 
+@pytest.mark.parametrize("score", [False, True])
+def test_grad_second_moment_matches_oracle(score):
+    # J = sum_s gL_s L_s + sum_s gL2_s L2_s, L2 = ln <w^2> (flag HE_FK_GRAD_MOMENT2)
+    from paper_1703_08977_amd import _lib
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, ckpt_every=50)
+    n = 2048
+    e, ckpt, s, x0 = _forward(cfg, n)
+    gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
+    gL2 = np.array([0.0, 0.5, 0.0, -0.8, 1.2])
+    flags = _lib.GRAD_MOMENT2 | (_lib.GRAD_SCORE if score else 0)
+    got = _grad(e, ckpt, s, cfg, np.concatenate([gL, gL2]), flags=flags)
+    ref = oracle.grad_objective(cfg, np.arange(n), x0.t().contiguous().cpu().numpy(), 200, 50, gL, score=score,
+                                gL2=gL2)
+    assert np.abs(got - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-3), (got, ref)
+
+
+def test_weight_variance_gradient_through_autograd_against_central_differences():
+    # d ln(<w^2>/<w>^2)(T) / d(alpha, beta) through the autograd wrapper, against central
+    # differences of the GPU forward map at the same start positions and noise
+    import torch
+    from paper_1703_08977_amd.autograd import log_space_moments, weight_variance
+    cfg = W.get("he_1s_pade_grad_256k", n_walkers=1 << 16, n_steps=500, sample_every=50, ckpt_every=50)
+    theta = torch.tensor([2.0, 0.25], dtype=torch.float64, requires_grad=True)
+    L, L2 = log_space_moments(theta, cfg)
+    V = weight_variance(L, L2)
+    V.backward()
+    e, ckpt, s, x0 = _forward(cfg)
+    fd = []
+    for d in range(2):
+        vals = []
+        for sgn in (+1, -1):
+            th = list(cfg["theta"])
+            th[d] += sgn * 1e-5
+            _, _, sp, _ = _forward(dict(cfg, theta=th), x0=x0)
+            h = sp.cpu().numpy()
+            vals.append(float((2 * h[-1, 0] + np.log(h[-1, 3])) - 2 * (h[-1, 0] + np.log(h[-1, 1])) + np.log(h[-1, 6])))
+        fd.append((vals[0] - vals[1]) / 2e-5)
+    fd = np.array(fd)
+    assert np.abs(theta.grad.numpy() - fd).max() <= 1e-6 * max(np.abs(fd).max(), 1e-3), (theta.grad, fd)
+
+
 def test_grad_full_size_against_central_differences():
     # 2^18 walkers x 1000 steps, checkpoints every 50: d E(T=2) / d(alpha, beta) against
     # central differences of the GPU forward map at the same start positions and noise.
@@ -145,6 +186,10 @@ def test_grad_rejects_unsupported_cases():
     nb = api.he_fk_grad_scratch_bytes(e.p, 100, 50, 50)
     scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = torch.empty(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.HeFkError) as ei:
+        api.he_fk_grad(e.p, ckpt.data_ptr(), s.data_ptr(), gL, 100, 50, 50, 4, scratch.data_ptr(), nb,
+                       d.data_ptr())
+    assert ei.value.code == _lib.HE_FK_EINVAL
     with pytest.raises(_lib.HeFkError) as ei:
         api.he_fk_grad(e.p, ckpt.data_ptr(), s.data_ptr(), gL, 100, 50, 50, 0, scratch.data_ptr(), nb - 1,
                        d.data_ptr())

@@ -237,6 +237,15 @@ def test_reverse_sweep_host_build_matches_complex_step(over, ckpt_every):
         assert abs(got[d] - ref[d]) <= 1e-11 * max(abs(ref[d]), 1e-3)
     # P = sum_s g_s p_is sums to sum_s g_s over walkers
     assert abs(a[:, 2].sum() - gL.sum()) < 1e-12
+    # with weights on ln <w^2> as well
+    gL2 = np.array([0.0, 0.5, 0.0, -0.8, 1.2])
+    a = adjoint_host_run(cfg, ids, 200, 50, ckpt_every, r["samples"], gL, gL2)
+    got = a[:, :2].sum(axis=0)
+    ref = oracle.grad_objective(cfg, ids, r["x0"], 200, 50, gL, gL2=gL2)
+    for d in range(2):
+        assert abs(got[d] - ref[d]) <= 1e-11 * max(abs(ref[d]), 1e-3)
+    assert abs(a[:, 3].sum() - gL2.sum()) < 1e-12                 # the shares q_is sum to one per row
+    assert abs(a[:, 2].sum() - gL.sum() - 2 * gL2.sum()) < 1e-12
 
 
 def test_binary64_step_functions_against_the_c_library():
