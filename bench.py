@@ -35,9 +35,12 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 steps for the speedup (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16384)
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
+    ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle"],
                     help="copy: a plain 1 GiB device copy, three times (the reference reading of the HBM "
-                         "byte counters FETCH_SIZE / WRITE_SIZE)")
+                         "byte counters FETCH_SIZE / WRITE_SIZE); oracle: time the CPU oracle alone on the "
+                         "4096-walker ground state in full and on walkers 0..65535 of the Pade ground state "
+                         "at dt = 0.002")
     return ap.parse_args()
 
 
@@ -152,6 +155,27 @@ def cpu_baseline(cfg, n_walkers):
                       (n_walkers - 1, cfg["n_steps"], t1 - t0, t2 - t1, ws / (t2 - t1), cpu_model())}
 
 
+def oracle_timing(threads=0):
+    """Walker-steps/s of the CPU oracle (start ensemble timed apart) on two workloads."""
+    import numpy as np
+    import oracle
+    from paper_1703_08977_amd import workloads as W
+    if threads > 0:
+        oracle.set_num_threads(threads)
+    out = {"mode": "oracle", "threads": oracle.num_threads(), "cpu": cpu_model(), "runs": []}
+    for name, n in (("he_1s_expo_4k", 4096), ("he_1s_pade_1m", 1 << 16)):
+        cfg = W.get(name, dt=0.002) if name == "he_1s_pade_1m" else W.get(name)
+        ids = np.arange(n)
+        t0 = time.perf_counter()
+        x, _ = oracle.init(cfg, ids)
+        t1 = time.perf_counter()
+        oracle.propagate(cfg, ids, x, np.zeros(n), 0, cfg["n_steps"], cfg["sample_every"], record=False)
+        t2 = time.perf_counter()
+        out["runs"].append({"workload": name, "walkers": n, "steps": cfg["n_steps"], "start_s": t1 - t0,
+                            "propagate_s": t2 - t1, "walker_steps_per_s": n * cfg["n_steps"] / (t2 - t1)})
+    print(json.dumps(out), flush=True)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -167,6 +191,9 @@ def main():
     args = parse()
     if args.mode == "copy":
         copy_reference()
+        return
+    if args.mode == "oracle":
+        oracle_timing(args.oracle_threads)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "

@@ -269,3 +269,8 @@ def grad_objective(cfg, ids, y0, n_steps, sample_every, gL, score=False, gL2=Non
 
 def num_threads() -> int:
     return int(lib().ofk_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from here on."""
+    lib().ofk_set_num_threads(int(n))

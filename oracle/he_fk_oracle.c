@@ -714,6 +714,16 @@ int ofk_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from here on (timing runs). */
+void ofk_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* The propagation noise of step k for many walkers: out [n][6]. */
 void ofk_noise_bulk(const ofk_params* p, uint64_t k, const uint64_t* ids, int64_t n, double* out)
 {

@@ -648,3 +648,14 @@ def test_bridge_weight_of_one_step_next_to_the_node(plain):
     got = lb[live] - la[live]
     assert np.all(got <= 0.0) and got.min() < -1e-3
     assert np.abs(got - expect[live]).max() < 5e-3 * np.abs(expect[live]).max() + 1e-12
+
+
+@pytest.mark.parametrize("theta", [(2.0, 0.25), (1.95, 0.33)])
+def test_one_step_weight_variance_is_the_local_energy_variance(theta):
+    # ln(<w^2>/<w>^2) after one trapezoid step of length dt from the |psi|^2 start equals
+    # dt^2 Var(E_L) to leading order in dt (the variance criterion used to tune the trial)
+    cfg = W.get("he_1s_pade_grad_256k", theta=[theta[0], theta[1], 0.5, 0.0], dt=1e-4, n_steps=1,
+                sample_every=1)
+    r = oracle.run(cfg, np.arange(1 << 15), 1, 1)
+    J = (est.log_mean_square_weight(r["samples"]) - 2 * est.log_mean_weight(r["samples"]))[1] / cfg["dt"] ** 2
+    assert abs(J / r["el0"].var() - 1.0) < 0.01
