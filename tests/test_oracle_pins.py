@@ -659,3 +659,36 @@ def test_one_step_weight_variance_is_the_local_energy_variance(theta):
     r = oracle.run(cfg, np.arange(1 << 15), 1, 1)
     J = (est.log_mean_square_weight(r["samples"]) - 2 * est.log_mean_weight(r["samples"]))[1] / cfg["dt"] ** 2
     assert abs(J / r["el0"].var() - 1.0) < 0.01
+
+
+def test_score_weighted_gradients_reduce_to_the_variational_formulas():
+    # As dt -> 0, one step from the |psi|^2 start: d E(dt)/d theta (score term included) tends to
+    # the variational-energy gradient <d_theta E_L> + cov(E_L, s), and the gradient of the one-step
+    # weight variance / dt^2 tends to that of Var(E_L), 2 <(E_L - <E_L>) d_theta E_L> +
+    # cov((E_L - <E_L>)^2, s), with s = 2 d ln psi / d theta; both on the same samples.  This pins the
+    # start-law weights (p - 1/N) and (q - 1/N) of the score term.
+    dt = 1e-5
+    cfg = W.get("he_1s_pade_grad_256k", dt=dt, n_steps=1, sample_every=1)
+    ids = np.arange(1 << 13)
+    y0, el0 = oracle.init(cfg, ids)
+
+    def d_el(d, h=1e-6):
+        out = np.zeros(len(y0))
+        for sgn in (1, -1):
+            th = list(cfg["theta"])
+            th[d] += sgn * h
+            c = dict(cfg, theta=th)
+            out += sgn * np.array([oracle.trial_eval(c, y).el for y in y0])
+        return out / (2 * h)
+
+    dev = el0 - el0.mean()
+    g_e = oracle.grad_objective(cfg, ids, y0, 1, 1, np.array([1 / dt, -1 / dt]), score=True)
+    g_v = oracle.grad_objective(cfg, ids, y0, 1, 1, np.array([0.0, -2 / dt ** 2]), score=True,
+                                gL2=np.array([0.0, 1 / dt ** 2]))
+    for d in range(2):
+        de = d_el(d)
+        s = 2 * oracle.dlnpsi_dtheta(cfg, y0, d)
+        ref_e = de.mean() + np.mean(dev * (s - s.mean()))
+        ref_v = np.mean(2 * dev * de) + np.mean((dev ** 2 - np.mean(dev ** 2)) * (s - s.mean()))
+        assert abs(g_e[d] - ref_e) < 3e-3 * abs(ref_e), (d, g_e[d], ref_e)
+        assert abs(g_v[d] - ref_v) < 3e-3 * abs(ref_v), (d, g_v[d], ref_v)
