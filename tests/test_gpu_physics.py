@@ -62,6 +62,24 @@ def test_ground_state_energy_bounds():
     assert EXACT_1S - 5 * err - 5e-4 < E < EXACT_1S + 2e-3, (E, err)
 
 
+@pytest.mark.parametrize("name,exact,T", [("he_2P_pz_16m", -2.123843086498093, 3.0),
+                                          ("he_2tripS_4m", -2.17522937823679130, 4.0)])
+def test_fixed_node_energies_lie_above_the_exact_ones(name, exact, T):
+    # Absorbing at the trial's node gives the lowest energy of that nodal pocket: with the inexact
+    # P_z node above the exact 2^1P energy, with the exact triplet node approaching 2^3S from above
+    # as T grows (mixed precision, 2^22 walkers; 5 sigma of the walker-block jackknife)
+    from paper_1703_08977_amd import Ensemble
+    from paper_1703_08977_amd.stats import jackknife
+    cfg = W.get(name, n_walkers=1 << 22)
+    cfg = dict(cfg, n_steps=int(round(T / cfg["dt"])))
+    e = Ensemble(cfg).init()
+    e.propagate(0, cfg["n_steps"], cfg["sample_every"])
+    dts = cfg["dt"] * cfg["sample_every"]
+    E, err = jackknife(e.block_rows(cfg["n_steps"], cfg["sample_every"]).cpu().numpy(), dts, cfg["e_ref"], "window")
+    assert E > exact - 5 * err, (E, err)
+    assert E < exact + 0.02, (E, err)
+
+
 def test_exact_trial_has_zero_variance_energy():
     # Z = 2 without 1/r12 and the exact trial: every estimator gives -4 with zero spread
     from paper_1703_08977_amd import Ensemble, he_fk_energy
