@@ -159,3 +159,25 @@ class Ensemble:
         """Host copies: x [N,6] (float64), lnw [N], el [N]."""
         return (self.x.double().t().contiguous().cpu().numpy(), self.lnw.cpu().numpy(),
                 self.el.double().cpu().numpy())
+
+
+def run(cfg: dict, n_walkers: int | None = None, seed: int | None = None) -> dict:
+    """One whole pass of the path for a workload dict: start ensemble, propagation over
+    cfg["n_steps"] steps sampled every cfg["sample_every"], and the estimators.
+
+    Returns host arrays: the sample rows, L(t_s), the finite-difference energies E_fd, the
+    window energy over [T/2, T] with its walker-block jackknife error, the mixed estimator and
+    the ESS at every sample time."""
+    from .stats import jackknife
+    c = dict(cfg) if seed is None else dict(cfg, seed=seed)
+    ens = Ensemble(c, n_walkers=n_walkers).init()
+    n_steps, se = c["n_steps"], c["sample_every"]
+    rows = ens.propagate(0, n_steps, se).cpu().numpy()
+    dts = c["dt"] * se
+    e_fd, aux, _ = he_fk_energy(rows, dts, c["e_ref"], "fd")
+    e_win = float(he_fk_energy(rows, dts, c["e_ref"], "window")[0][0])
+    e_mix = he_fk_energy(rows, dts, c["e_ref"], "mixed")[0]
+    _, err = jackknife(ens.block_rows(n_steps, se).cpu().numpy(), dts, c["e_ref"], "window")
+    return {"samples": rows, "t": np.arange(len(rows)) * dts, "L": aux[:, 0], "ess": aux[:, 1], "E_fd": e_fd,
+            "E_window": e_win, "E_window_jackknife": float(err), "E_mixed": e_mix}
+

@@ -320,3 +320,16 @@ def test_ensemble_beyond_2_31_array_elements():
     assert abs(L - log_mean_weight(s)[-1]) < 1e-12
     del e
     torch.cuda.empty_cache()
+
+
+def test_run_helper_matches_the_oracle_estimators():
+    from oracle import estimators as est
+    from paper_1703_08977_amd import run
+    cfg = W.get("he_1s_expo_4k")
+    out = run(cfg)
+    r = oracle.run(cfg, np.arange(cfg["n_walkers"]), cfg["n_steps"], cfg["sample_every"])
+    dts = cfg["dt"] * cfg["sample_every"]
+    assert np.abs(out["L"] - log_mean_weight(r["samples"])).max() < TOL
+    assert np.abs(out["E_fd"] - est.e_fd(r["samples"], dts, cfg["e_ref"])).max() < 1e-9
+    assert abs(out["E_window"] - est.e_window(r["samples"], dts, cfg["e_ref"])) < 1e-10
+    assert np.isfinite(out["E_window_jackknife"]) and out["E_window_jackknife"] > 0
