@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "he_fk_oracle.c")
 _LIB = os.path.join(_HERE, "libhefk_oracle.so")
 
-TRIALS = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4}
+TRIALS = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4, "pz_sum": 5}
 NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}
 FLAG_PLAIN = 1   # plain Feynman-Kac walk (no drift, integrand V)

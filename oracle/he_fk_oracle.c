@@ -54,6 +54,7 @@
 #define OFK_TRIAL_TRIPLET 2 /* [exp(-A r1 - a r2) - exp(-A r2 - a r1)] * Jastrow     */
 #define OFK_TRIAL_PZ 3      /* [z2 exp(-A r1 - a r2) + s z1 exp(-A r2 - a r1)] * Jastrow */
 #define OFK_TRIAL_TRIPLET_R0 4 /* [(r0 - r1) exp(-A r1 - a r2) - (r0 - r2) exp(-A r2 - a r1)] * Jastrow */
+#define OFK_TRIAL_PZ_SUM 5  /* (z1 + z2) [exp(-A r1 - a r2) + exp(-A r2 - a r1)] * Jastrow (trial function 7) */
 
 #define OFK_NOISE_GAUSS 0
 #define OFK_NOISE_PM1 1
@@ -208,7 +209,8 @@ typedef struct {
 
 static int trial_has_node(const ofk_params* p)
 {
-    return p->trial == OFK_TRIAL_TRIPLET || p->trial == OFK_TRIAL_PZ || p->trial == OFK_TRIAL_TRIPLET_R0;
+    return p->trial == OFK_TRIAL_TRIPLET || p->trial == OFK_TRIAL_PZ || p->trial == OFK_TRIAL_TRIPLET_R0 ||
+           p->trial == OFK_TRIAL_PZ_SUM;
 }
 
 /*
@@ -282,6 +284,26 @@ void ofk_trial_eval(const ofk_params* p, const double y[6], ofk_eval* out)
         lP2 = (p1 * (a * a - 2.0 * a / r2) - q * (A * (2.0 + A * p2) - 2.0 * (1.0 + A * p2) / r2)) / D;
         lnPhi = -A * r1 - a * r2 + log(fabs(D));
         sign = (D > 0.0) ? 1 : ((D < 0.0) ? -1 : 0);
+    } else if (p->trial == OFK_TRIAL_PZ_SUM) {
+        /* Phi = Zs S, Zs = z1 + z2 (a linear function: Lap Zs = 0, grad_i Zs = zhat), S = f + g,
+           f = exp(-A r1 - a r2), g = exp(-A r2 - a r1) = f q, q = exp((A - a)(r1 - r2)).
+           grad_i Phi / Phi = zhat / Zs + grad_i S / S,
+           Lap_i Phi / Phi = Lap_i S / S + 2 zhat . grad_i S / (Zs S). */
+        double Zs = R1[2] + R2[2];
+        double q = exp((A - a) * (r1 - r2));
+        double Sn = 1.0 + q; /* S / f */
+        double gs1 = -(A + a * q) / Sn, gs2 = -(a + A * q) / Sn; /* grad_i S / S = gs_i h_i */
+        for (int k = 0; k < 3; ++k) {
+            double zh = (k == 2) ? 1.0 : 0.0;
+            gP1[k] = zh / Zs + gs1 * h1[k];
+            gP2[k] = zh / Zs + gs2 * h2[k];
+        }
+        double lS1 = ((A * A - 2.0 * A / r1) + q * (a * a - 2.0 * a / r1)) / Sn;
+        double lS2 = ((a * a - 2.0 * a / r2) + q * (A * A - 2.0 * A / r2)) / Sn;
+        lP1 = lS1 + 2.0 * gs1 * h1[2] / Zs;
+        lP2 = lS2 + 2.0 * gs2 * h2[2] / Zs;
+        lnPhi = log(fabs(Zs)) - A * r1 - a * r2 + log(Sn);
+        sign = (Zs > 0.0) ? 1 : ((Zs < 0.0) ? -1 : 0);
     } else { /* OFK_TRIAL_PZ */
         /* Phi = z2 f + s z1 g, g = f rho, rho = exp((A - a)(r1 - r2)); Phi = f P,
            P = z2 + s z1 rho.  grad z1 = zhat for electron 1 (likewise z2).

@@ -3,7 +3,7 @@
 Each workload is a plain dict read by both the HIP path (through the
 binding) and the CPU oracle, so that both draw the same Philox streams.
 Keys:
-  trial        "expo" | "pade" | "triplet" | "pz" | "triplet_r0"
+  trial        "expo" | "pade" | "triplet" | "pz" | "triplet_r0" | "pz_sum"
   theta        [orbital exponent, Jastrow beta, Jastrow c, second exponent a, r0]
   sym          +1 / -1 (P_z trial: singlet "+" or triplet "-" combination)
   Z, ee        nuclear charge; 1 if the potential holds +1/r12
@@ -90,9 +90,18 @@ PAPER_FN4_1M = dict(
     PAPER_FN3_1M, name="he_2tripS_fn4_1m", theta=[0.67180691, 0.0, 0.0, 2.00411836, 1.0, 0.0],
     e_ref=-2.17315)
 
+# The paper's P_z run (Table 5): trial function 7, (z1 + z2)[e^{-a1 r1 - a2 r2} + e^{-a2 r1 - a1 r2}],
+# whose exponents are not printed.  Reconstruction: a1 = 2 (the He+ 1s exponent), a2 = 0.25, whose
+# mean local energy over |psi|^2, -2.0645(8) from 2^17 samples, matches the printed trial energy
+# lambda0 = -2.06460746 used as e_ref.  The outer electron reaches r ~ 10, so the start ensemble takes
+# 2000 Metropolis steps of box width 1.
+PAPER_FN7_1M = dict(
+    PAPER_FN3_1M, name="he_2P_fn7_1m", trial="pz_sum", theta=[2.0, 0.0, 0.0, 0.25, 0.0, 0.0],
+    e_ref=-2.06460746, n_metropolis=2000, metropolis_sigma=1.0)
+
 WORKLOADS = {w["name"]: w for w in
              (HE_GROUND_EXPO_4K, HE_GROUND_PADE_1M, HE_TRIPLET_4M, HE_GRAD_PADE_256K, HE_PZ_16M,
-              PAPER_FN3_1M, PAPER_FN4_1M, PAPER_FN5_1M)}
+              PAPER_FN3_1M, PAPER_FN4_1M, PAPER_FN5_1M, PAPER_FN7_1M)}
 
 # Closed-form systems.
 # Z = 2 without 1/r12 and the exact product of hydrogenic 1s orbitals: E_L = -4 exactly.
