@@ -60,6 +60,11 @@ extern "C" {
    the paper's trial functions 3-5 for the 2^3S state (r0 = t4, alpha1 = t0, alpha2 = t3;
    no Jastrow factor when t2 = 0); node r1 = r2 */
 #define HE_FK_TRIAL_TRIPLET_R0 4
+/* (z1 + z2) [exp(-t0 r1 - t3 r2) + exp(-t0 r2 - t3 r1)] exp(t2 r12 / (1 + t1 r12)): the
+   paper's trial function 7 for the P_z state ((r1 cos th1 + r2 cos th2) times the symmetric
+   exponential pair, alpha1 = t0, alpha2 = t3, no Jastrow factor when t2 = 0); its node is the
+   plane z1 + z2 = 0 of the necessary nodal condition z1 = -z2 */
+#define HE_FK_TRIAL_PZ_SUM 5
 
 #define HE_FK_FP64 0  /* coordinates, drift, E_L, ln w all binary64                       */
 #define HE_FK_MIXED 1 /* coordinates, drift, E_L binary32; ln w, reductions binary64     */
@@ -172,7 +177,7 @@ size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, i
 /*
  * he_fk_propagate: advance every walker over global steps [step0, step0 + n_steps)
  * (drifted diffusion after eq. (4), discretised as in the paper's random-walk
- * construction; absorption at the node for the TRIPLET, TRIPLET_R0 and PZ trials):
+ * construction; absorption at the node for the TRIPLET, TRIPLET_R0, PZ and PZ_SUM trials):
  *   Y' = Y + dt b(Y) + sqrt(dt) xi_k,  b = grad ln|psi_T|;
  *   absorbed (lnw = -inf, frozen) iff sign psi_T(Y') != sign psi_T(Y) or psi_T(Y') = 0;
  *   else ln w updated by the quadrature rule and Y = Y'.

@@ -22,7 +22,7 @@ HE_FK_ENONFINITE = -3
 HE_FK_EALLDEAD = -4
 HE_FK_ESCRATCH = -5
 
-TRIAL = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4}
+TRIAL = {"expo": 0, "pade": 1, "triplet": 2, "pz": 3, "triplet_r0": 4, "pz_sum": 5}
 PRECISION = {"fp64": 0, "mixed": 1}
 NOISE = {"gauss": 0, "pm1": 1}
 QUAD = {"trapezoid": 0, "right": 1}

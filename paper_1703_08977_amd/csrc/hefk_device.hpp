@@ -16,14 +16,15 @@
 
 namespace hefk {
 
-enum : int { TRIAL_EXPO = 0, TRIAL_PADE = 1, TRIAL_TRIPLET = 2, TRIAL_PZ = 3, TRIAL_TRIPLET_R0 = 4 };
+enum : int { TRIAL_EXPO = 0, TRIAL_PADE = 1, TRIAL_TRIPLET = 2, TRIAL_PZ = 3, TRIAL_TRIPLET_R0 = 4, TRIAL_PZ_SUM = 5 };
 // noise kinds of the kernels: Gaussian under contract 1, Gaussian under contract 2, +-1 walk
 enum : int { NOISE_G1 = 0, NOISE_G2 = 1, NOISE_PM1 = 2 };
 enum : uint32_t { PHASE_INIT = 0, PHASE_METROPOLIS = 1, PHASE_GAUSS = 2, PHASE_PM1 = 3 };
 
 template <int TRIAL>
 struct has_node {
-    static constexpr bool value = (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_PZ || TRIAL == TRIAL_TRIPLET_R0);
+    static constexpr bool value =
+        (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_PZ || TRIAL == TRIAL_TRIPLET_R0 || TRIAL == TRIAL_PZ_SUM);
 };
 
 // ---------------------------------------------------------------------------
@@ -382,6 +383,36 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2
         const R cross = (g1 * g.p1 * g.i1 - g2 * g.p2 * g.i2) * g.i12;  // g1 h1.h12 - g2 h2.h12
         el = (R)-0.5 * (l1 + l2) - j.up * cross - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
+    } else if (TRIAL == TRIAL_PZ_SUM) {
+        // Phi = (z1 + z2)(f + g) (trial function 7): with Zs = z1 + z2 and S = f + g,
+        // grad_i Phi / Phi = zhat / Zs + gs_i h_i, gs_1 = -(A t1 + a t2) / (t1 + t2),
+        // gs_2 = -(a t1 + A t2) / (t1 + t2); Lap_i Phi / Phi = Lap_i S / S + 2 gs_i z_i / (r_i Zs)
+        const Jas<R> j = jastrow(p, g);
+        const R d = (p.A - p.a) * (g.r1 - g.r2);
+        const bool lo = d <= (R)0;
+        const R e = m::exp_(lo ? d : -d);
+        const R t1 = lo ? (R)1 : e;
+        const R t2 = lo ? e : (R)1;
+        const R iS = m::rcp_(t1 + t2);
+        const R z1 = y[2], z2 = y[5];
+        const R Zs = z1 + z2;
+        const R iZ = m::rcp_(Zs);
+        const R g1 = -(p.A * t1 + p.a * t2) * iS;
+        const R g2 = -(p.a * t1 + p.A * t2) * iS;
+        const R a1 = g1 * g.i1, a2 = g2 * g.i2;
+        drift_from(y, g, a1, a2, j.up * g.i12, b);
+        b[2] += iZ;
+        b[5] += iZ;
+        if (gphi2)
+            *gphi2 = g1 * g1 + g2 * g2 + (R)2 * iZ * (a1 * z1 + a2 * z2 + iZ);
+        const R l1 = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) + t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iS +
+                     (R)2 * a1 * z1 * iZ;
+        const R l2 = (t1 * (p.a * p.a - (R)2 * p.a * g.i2) + t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iS +
+                     (R)2 * a2 * z2 * iZ;
+        // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12: the zhat / Zs terms cancel
+        const R cr = (a1 * g.p1 - a2 * g.p2) * g.i12;
+        el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        sign = (Zs > (R)0) ? 1 : ((Zs < (R)0) ? -1 : 0);
     } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
@@ -446,6 +477,7 @@ HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
         return lnmax + f64::log(::fabs(D)) + U;
     }
     const double e = f64::exp(lo ? d : -d);
+    if (TRIAL == TRIAL_PZ_SUM) return lnmax + f64::log(::fabs(y[2] + y[5]) * (1.0 + e)) + U;
     const double P = y[5] * (lo ? 1.0 : e) + p.sym * y[2] * (lo ? e : 1.0);
     return lnmax + f64::log(::fabs(P)) + U;
 }

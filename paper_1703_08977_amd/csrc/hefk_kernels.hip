@@ -217,6 +217,7 @@ KernelFn pick_propagate_t(int trial, int noise)
         case TRIAL_PADE: return pick_propagate<R, TRIAL_PADE, EXT>(noise);
         case TRIAL_TRIPLET: return pick_propagate<R, TRIAL_TRIPLET, EXT>(noise);
         case TRIAL_TRIPLET_R0: return pick_propagate<R, TRIAL_TRIPLET_R0, EXT>(noise);
+        case TRIAL_PZ_SUM: return pick_propagate<R, TRIAL_PZ_SUM, EXT>(noise);
         default: return pick_propagate<R, TRIAL_PZ, EXT>(noise);
     }
 }
@@ -236,6 +237,7 @@ KernelFn pick_init_r(int trial)
         case TRIAL_PADE: return init_kernel<R, TRIAL_PADE>;
         case TRIAL_TRIPLET: return init_kernel<R, TRIAL_TRIPLET>;
         case TRIAL_TRIPLET_R0: return init_kernel<R, TRIAL_TRIPLET_R0>;
+        case TRIAL_PZ_SUM: return init_kernel<R, TRIAL_PZ_SUM>;
         default: return init_kernel<R, TRIAL_PZ>;
     }
 }
@@ -257,7 +259,7 @@ static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int check_params(const he_fk_params* p)
 {
     if (!p) return HE_FK_EINVAL;
-    if (p->trial < HE_FK_TRIAL_EXPO || p->trial > HE_FK_TRIAL_TRIPLET_R0) return HE_FK_EINVAL;
+    if (p->trial < HE_FK_TRIAL_EXPO || p->trial > HE_FK_TRIAL_PZ_SUM) return HE_FK_EINVAL;
     if (p->trial == HE_FK_TRIAL_PZ && p->sym != 1 && p->sym != -1) return HE_FK_EINVAL;
     if (p->ee != 0 && p->ee != 1) return HE_FK_EINVAL;
     if (p->noise != HE_FK_NOISE_GAUSS && p->noise != HE_FK_NOISE_PM1) return HE_FK_EINVAL;

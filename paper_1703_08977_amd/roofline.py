@@ -103,6 +103,12 @@ def _trial(c: _Count, f, trial: str):
         # g_i / r_i (2), w (1), drift, cross term (5), E_L (8), sign (3)
         c.ops(4 + 2 + 8 + 16 + 2 + 1 + drift + 5 + 8 + 3)
         return
+    if trial == "pz_sum":
+        c.fn(f, "rcp")  # 1 / (z1 + z2)
+        # t1 + t2 (1), z1 + z2 (1), g1, g2 (2 x 3), a_i (2), w (1), drift, z terms (2), node-gradient
+        # Laplacian ratios (2 x 8), cross term (3), E_L (8), sign (3)
+        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 16 + 3 + 8 + 3)
+        return
     # P_z: sym t2 (1), P (2), k1, k2 (2 x 4), a1, a2 (2 x 2), s1, s2 (2), w (1), drift, z terms (2),
     # Laplacian ratios (2 x 7), cross term (5), E_L (8), sign (3)
     c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 14 + 5 + 8 + 3)
@@ -138,6 +144,6 @@ def fp32_flops_per_walker_step(cfg: dict) -> float:
     """binary32 floating-point operations of one mixed step (fma = 2, transcendental = 1)."""
     if cfg.get("precision", "fp64") != "mixed":
         return 0.0
-    base = {"expo": 50, "pade": 85, "triplet": 125, "triplet_r0": 130, "pz": 140}[cfg["trial"]]
+    base = {"expo": 50, "pade": 85, "triplet": 125, "triplet_r0": 130, "pz": 140, "pz_sum": 130}[cfg["trial"]]
     noise = 0 if cfg.get("noise", "gauss") == "pm1" else 3 * 6 + 6
     return float(12 * 2 + base + noise)

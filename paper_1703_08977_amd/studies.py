@@ -12,7 +12,7 @@ c4  tuning of (alpha, beta) by 20 adjoint-gradient steps, 2^18 walkers: sigma^2(
     spread, ESS and sigma(E_L) before and after.
 c5  P_z (2^1P) "+", 2^24 walkers, dt = 0.0005, T = 6: mixed vs FP64, paired difference,
     seed-to-seed errors and the time to a 1e-5 Ha statistical error.
-paper  the setting of Tables 1 and 2: trial functions 3 and 5, the +-1 walk at scale 30
+paper  the setting of Tables 1, 2 and 5: trial functions 3, 4, 5 and 7, the +-1 walk at scale 30
     (dt = 1/900), right end-point sum, ln z_t at t = 8..48 and the least-squares fit
     ln z_t / t = b + a / t, lambda1 = lambda0 - b.
 longt  long projection times as in the paper (T = 48) for the ground state (Pade-Jastrow,
@@ -192,7 +192,7 @@ def paper(seeds=8):
     from . import Ensemble, he_fk_energy
     from . import workloads as W
     out = {}
-    for name in ("he_2tripS_fn3_1m", "he_2tripS_fn4_1m", "he_2tripS_fn5_1m"):
+    for name in ("he_2tripS_fn3_1m", "he_2tripS_fn4_1m", "he_2tripS_fn5_1m", "he_2P_fn7_1m"):
         for prec in ("mixed", "fp64"):
             cfg = W.get(name, precision=prec)
             t_fit = np.array(cfg["t_fit"], dtype=np.float64)
@@ -220,11 +220,12 @@ def paper(seeds=8):
             table = [{"t": float(t), "z_t": float(np.exp(lnz[:, i].mean())), "ln_z_t": float(lnz[:, i].mean()),
                       "ln_z_t_over_t": float(lnz[:, i].mean() / t), "sigma": float(lnz[:, i].std(ddof=1) / t)}
                      for i, t in enumerate(t_fit)]
+            exact = EXACT["1P"] if cfg["trial"] == "pz_sum" else EXACT["3S"]
             out["%s_%s" % (name, prec)] = {"lambda0": cfg["e_ref"], "lambda1": m, "lambda1_se": se,
-                                           "lambda1_minus_exact": m - EXACT["3S"], "table": table,
+                                           "lambda1_minus_exact": m - exact, "table": table,
                                            "wall_s": float(np.mean(walls)), "seeds": seeds}
-    out["paper_lambda1_context"] = {"fn3": -2.17536239, "fn5": -2.1752508}
-    out["exact"] = EXACT["3S"]
+    out["paper_lambda1_context"] = {"fn3": -2.17536239, "fn5": -2.1752508, "fn7": -2.1250716}
+    out["exact"] = {"3S": EXACT["3S"], "1P": EXACT["1P"]}
     return out
 
 

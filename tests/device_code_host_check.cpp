@@ -107,6 +107,7 @@ void dispatch(const Cfg& c, unsigned long long g)
         case TRIAL_PADE: dispatch_noise<R, TRIAL_PADE>(c, g); break;
         case TRIAL_TRIPLET: dispatch_noise<R, TRIAL_TRIPLET>(c, g); break;
         case TRIAL_TRIPLET_R0: dispatch_noise<R, TRIAL_TRIPLET_R0>(c, g); break;
+        case TRIAL_PZ_SUM: dispatch_noise<R, TRIAL_PZ_SUM>(c, g); break;
         default: dispatch_noise<R, TRIAL_PZ>(c, g); break;
     }
 }

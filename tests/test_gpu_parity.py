@@ -49,7 +49,7 @@ def _compare(g, r, tol=TOL, node=False):
 
 
 def _has_node(cfg):
-    return cfg["trial"] in ("triplet", "pz", "triplet_r0")
+    return cfg["trial"] in ("triplet", "pz", "triplet_r0", "pz_sum")
 
 
 def test_c1_full_parity():
@@ -77,6 +77,8 @@ CASES = [
     ("he_1s_pade_1m", dict(dt=0.01, drift_limit=0.5, contract=2)),
     ("he_2tripS_fn3_1m", dict(precision="fp64")),
     ("he_2tripS_fn4_1m", dict(precision="fp64")),
+    ("he_2P_fn7_1m", dict(precision="fp64")),
+    ("he_2P_fn7_1m", dict(precision="fp64", noise="gauss", quad="trapezoid", dt=0.002, bridge=True)),
     ("he_2tripS_fn5_1m", dict(precision="fp64", noise="gauss", quad="trapezoid", dt=0.002)),
     # variants: plain Feynman-Kac walk, node-touch (bridge) weight
     ("he_1s_pade_1m", dict(dt=0.002, plain=True)),

@@ -200,6 +200,8 @@ HOST_CASES = [
     ("he_2tripS_4m", {"dt": 0.005, "plain": True, "bridge": True, "noise": "pm1"}),
     ("he_2P_pz_16m", {"dt": 0.005, "bridge": True}),
     ("he_2tripS_fn5_1m", {"precision": "fp64", "bridge": True}),
+    ("he_2P_fn7_1m", {"precision": "fp64", "n_metropolis": 300}),
+    ("he_2P_fn7_1m", {"precision": "fp64", "n_metropolis": 300, "noise": "gauss", "dt": 0.002, "bridge": True}),
 ]
 
 
