@@ -154,3 +154,31 @@ def test_bridge_weight_removes_the_missed_node_touches_of_the_brownian_walk():
     assert abs(b1 - b2) < tol, (b1, b2, tol)
     assert e2 - e1 < -5 * tol, (e1, e2, tol)       # end-point survival still falls with dt
     assert b2 < e2                                  # touches between steps lower the survival
+
+
+def test_bridge_is_exact_for_brownian_walkers_at_a_flat_node():
+    # Trial function 7 has the node plane z1 + z2 = 0.  Brownian walkers (potential off): the
+    # distance u = |z1 + z2| / sqrt(2) is a one-dimensional Brownian motion of variance t, which
+    # survives to T with probability erf(u0 / sqrt(2 T)).  Over the start ensemble that expectation
+    # is exact; with the bridge weight the walk reproduces it at any dt (sigma = sqrt(S (1 - S) / N)),
+    # the end-point test alone overshoots by O(sqrt dt).
+    from scipy.special import erf
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    T, n = 0.5, 1 << 22
+    for dt in (0.004, 0.001):
+        k = int(round(T / dt))
+        cfg = W.get("he_2P_fn7_1m", n_walkers=n, Z=1e-9, ee=0, e_ref=0.0, plain=True, noise="gauss",
+                    quad="trapezoid", dt=dt, n_steps=k, sample_every=k, precision="fp64")
+        S = {}
+        for bridge in (False, True):
+            e = Ensemble(dict(cfg, bridge=bridge)).init()
+            u0 = ((e.x[2] + e.x[5]).abs() / math.sqrt(2.0)).cpu().numpy()
+            exact = float(np.mean(erf(u0 / math.sqrt(2 * T))))
+            s = e.propagate(0, k, k).cpu().numpy()
+            S[bridge] = math.exp(s[-1, 0]) * s[-1, 1] / s[-1, 6]
+            del e
+            torch.cuda.empty_cache()
+        sig = math.sqrt(exact * (1 - exact) / n)
+        assert abs(S[True] - exact) < 5 * sig, (dt, S, exact, sig)
+        assert S[False] - exact > 5 * sig, (dt, S, exact, sig)
