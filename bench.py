@@ -197,7 +197,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "
-              "reduction, and this build measures one MI355X (requested --gpus %d)" % args.gpus, file=sys.stderr)
+              "reduction, and this benchmark measures one MI355X (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1703_08977_amd import workloads as W

@@ -8,7 +8,7 @@ Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s
 on the main VALU pipe, one operation per lane per clock (a wave64
 instruction occupies a 16-lane SIMD for 4 clocks).  This is the published
 78.6 TFLOP/s binary32 (and binary64) FMA rate divided by 2 flops; the 157.3
-TFLOP/s binary32 figure needs packed (v_pk_*) instructions, which this build
+TFLOP/s binary32 figure needs packed (v_pk_*) instructions, which this library
 does not use.
 
 Work: every elementary operation of the step's formulas counts one slot of
