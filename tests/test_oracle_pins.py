@@ -406,7 +406,7 @@ def _table(name):
 
 
 @pytest.mark.parametrize("name,tol", [("paper_table3.txt", 1e-6), ("paper_table4.txt", 1e-6),
-                                      ("paper_table2.txt", 1e-5)])
+                                      ("paper_table2.txt", 1e-5), ("paper_table5.txt", 1e-4)])
 def test_paper_ls_fit_columns(name, tol):
     tab, lam = _table(name)
     t, lsfit = tab[:, 0], tab[:, 5]
@@ -422,10 +422,22 @@ def test_paper_ls_fit_columns(name, tol):
     assert abs(E - lam["l1"]) < tol
 
 
+def test_paper_table1_weighted_fit():
+    # Table 1's lambda1 comes from ln(z_t)/t = b + a/t weighted by 1/sigma^2 (the estimator's weights)
+    tab, lam = _table("paper_table1.txt")
+    t, lnz, sig = tab[:, 0], tab[:, 2], tab[:, 4]
+    b, _ = est.fit_b_a(t, lnz / t, 1.0 / sig ** 2)
+    assert abs((lam["l0"] - b) - lam["l1"]) < 5e-6
+    L = np.concatenate([[0.0], lnz])
+    E, _ = est.e_fit(_rows_from_L(L), 8.0, lam["l0"], w=np.concatenate([[0.0], 1.0 / sig ** 2]))
+    assert abs(E - lam["l1"]) < 5e-6
+
+
 def test_paper_table_columns_consistent():
     # ln(z_t) and ln(z_t)/t columns agree with z_t (rounding of the print; Table 3 at
     # t = 40 prints ln z = 0.272223 where ln 1.312896 = 0.272235)
-    for name in ("paper_table2.txt", "paper_table3.txt", "paper_table4.txt"):
+    for name in ("paper_table1.txt", "paper_table2.txt", "paper_table3.txt", "paper_table4.txt",
+                 "paper_table5.txt"):
         tab, _ = _table(name)
         assert np.abs(np.log(tab[:, 1]) - tab[:, 2]).max() < 2e-5
         assert np.abs(tab[:, 2] / tab[:, 0] - tab[:, 3]).max() < 2e-6
