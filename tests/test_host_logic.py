@@ -137,8 +137,9 @@ def test_energy_estimators_match_oracle(n):
     assert np.abs(out - est.e_mixed(s)).max() < 1e-14
 
 
-@pytest.mark.parametrize("name,tol", [("paper_table3.txt", 1e-6), ("paper_table4.txt", 1e-6)])
-def test_energy_fit_reproduces_paper_tables(name, tol):
+@pytest.mark.parametrize("name,tol,weighted", [("paper_table3.txt", 1e-6, False), ("paper_table4.txt", 1e-6, False),
+                                               ("paper_table1.txt", 5e-6, True)])
+def test_energy_fit_reproduces_paper_tables(name, tol, weighted):
     rows, lam = [], {}
     for line in open(os.path.join(ROOT, "tests", "golden", name)):
         if line.startswith("# lambda0"):
@@ -147,7 +148,9 @@ def test_energy_fit_reproduces_paper_tables(name, tol):
         elif line.strip() and not line.startswith("#"):
             rows.append([float(v) for v in line.split()])
     tab = np.array(rows)
-    L = np.concatenate([[0.0], tab[:, 0] * tab[:, 5]])  # t * (ls-fit column), t = 0, 8, ..., 48
+    # t * (ls-fit column), or ln z_t with weights 1/sigma^2 (Table 1), at t = 0, 8, ..., 48
+    L = np.concatenate([[0.0], tab[:, 2] if weighted else tab[:, 0] * tab[:, 5]])
+    w = np.concatenate([[0.0], 1.0 / tab[:, 4] ** 2]) if weighted else None
     N = 150000
     s = np.zeros((len(L), 8))
     s[:, 0] = L + math.log(N)
@@ -155,7 +158,7 @@ def test_energy_fit_reproduces_paper_tables(name, tol):
     s[:, 3] = 1.0
     s[:, 4] = N
     s[:, 6] = N
-    out, _, rc = api.he_fk_energy(s, 8.0, lam["l0"], "fit")
+    out, _, rc = api.he_fk_energy(s, 8.0, lam["l0"], "fit", fit_w=w)
     assert rc == 0 and abs(out[0] - lam["l1"]) < tol
 
 
