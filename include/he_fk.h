@@ -179,8 +179,9 @@ size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, i
  * (drifted diffusion after eq. (4), discretised as in the paper's random-walk
  * construction; absorption at the node for the TRIPLET, TRIPLET_R0, PZ and PZ_SUM trials):
  *   Y' = Y + dt b(Y) + sqrt(dt) xi_k,  b = grad ln|psi_T|;
- *   absorbed (lnw = -inf, frozen) iff sign psi_T(Y') != sign psi_T(Y) or psi_T(Y') = 0;
- *   else ln w updated by the quadrature rule and Y = Y'.
+ *   Y = Y' and ln w updated by the quadrature rule, unless sign psi_T(Y') != sign psi_T(Y)
+ *   or psi_T(Y') = 0: then the walker is absorbed (lnw = -inf) and stays at Y' (x and el
+ *   of an absorbed walker are those of the first position found across the node).
  * With HE_FK_FLAG_PLAIN, b = 0 and the integrand is V - e_ref; with HE_FK_FLAG_BRIDGE
  * the node-touch survival term is added to ln w after the quadrature.
  * samples [n_steps / sample_every + 1][8] (device, binary64): row s is the

@@ -472,7 +472,8 @@ static double bridge_log_survival(const ofk_params* p, double g2a, double g2b)
  * marks a walker whose local energy went non-finite (kept NaN from then on).
  * Per step: Y' = Y + dt b(Y) + sqrt(dt) xi_k; if the trial has a node and
  * sign psi(Y') differs from sign psi(Y) (or psi(Y') = 0) the walker is
- * absorbed and frozen; otherwise, with the integrand e(Y) = E_L(Y) - e_ref,
+ * absorbed: it moves to Y' (with E_L(Y')) and stays there with lnw = -inf;
+ * otherwise, with the integrand e(Y) = E_L(Y) - e_ref,
  *   trapezoid: lnw -= (dt/2) [e(Y) + e(Y')],
  *   right:     lnw -=  dt    e(Y').
  * Plain Feynman-Kac (flag OFK_FLAG_PLAIN, eqs. (2)-(3) with f = 1): b = 0 (Brownian
@@ -506,7 +507,11 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
             ofk_eval nxt;
             ofk_trial_eval(p, yt, &nxt);
             if (node && (nxt.sign != cur.sign || nxt.sign == 0)) {
+                /* absorbed: weight zero from here on; the walker stays at the first
+                   position found across the node (the paper gives it none) */
                 w = -INFINITY;
+                memcpy(y, yt, sizeof(double) * 6);
+                cur = nxt;
             } else {
                 double fn = plain ? 0.0 : limit_factor(p, nxt.b);
                 double ebn = plain ? nxt.V - p->e_ref : fn * (nxt.el - p->e_ref);

@@ -36,6 +36,8 @@ struct has_node {
 namespace m {
 
 HD double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+HD double copysign_(double a, double b) { return __builtin_copysign(a, b); }
+HD float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
 HD float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 HD double sqrt_(double x) { return f64::sqrt(x); }
 HD double rcp_(double x) { return f64::rcp(x); }
@@ -43,6 +45,8 @@ HD double exp_(double x) { return f64::exp(x); }
 HD double expm1_(double x) { return ::expm1(x); }
 HD double log_(double x) { return f64::log(x); }
 HD double neg2log_(double x) { return f64::neg2log(x); }
+// the logarithm whose base the Box-Muller radius scale assumes: natural in binary64
+HD double logb_(double x) { return f64::log(x); }
 // sin(2 pi u), cos(2 pi u) for u in (0, 1)
 HD void sincos2pi(double u, double* s, double* c) { f64::sincos2pi(u, s, c); }
 
@@ -86,6 +90,15 @@ HD float neg2log_(float x)
     return __builtin_amdgcn_logf(x) * -1.3862943611198906f;
 #else
     return -2.0f * ::logf(x);
+#endif
+}
+// base-2 logarithm in binary32: one v_log_f32
+HD float logb_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x);
+#else
+    return ::log2f(x);
 #endif
 }
 HD void sincos2pi(float u, float* s, float* c)
@@ -181,30 +194,83 @@ HD void box_muller(R u1, R u2, R* a, R* b)
     *b = rad * s;
 }
 
-// Gaussian 6-vector number v of a phase, contract 1 (blocks 2v, 2v+1); returns
-// the spare uniform of word 2 of the second block in *spare (binary64).
+// The six uniforms of Gaussian vector v of a phase.  Contract 1: blocks 2v, 2v+1,
+// words 0..3 of the first and 0, 1 of the second, 32 bits each.
 template <typename R>
-HD void gauss6_c1(const Stream& st, uint32_t phase, uint32_t v, R xi[6], double* spare)
+HD void uniforms6_c1(const Stream& st, uint32_t phase, uint32_t v, R u[6])
 {
     const Words a = st.block(phase, 2u * v);
     const Words b = st.block(phase, 2u * v + 1u);
-    box_muller<R>(unit32(a.w[0], R()), unit32(a.w[1], R()), &xi[0], &xi[1]);
-    box_muller<R>(unit32(a.w[2], R()), unit32(a.w[3], R()), &xi[2], &xi[3]);
-    box_muller<R>(unit32(b.w[0], R()), unit32(b.w[1], R()), &xi[4], &xi[5]);
-    if (spare) *spare = unit32(b.w[2], 0.0);
+    u[0] = unit32(a.w[0], R());
+    u[1] = unit32(a.w[1], R());
+    u[2] = unit32(a.w[2], R());
+    u[3] = unit32(a.w[3], R());
+    u[4] = unit32(b.w[0], R());
+    u[5] = unit32(b.w[1], R());
 }
 
-// contract 2: one block, six 21-bit fields
+// contract 2: one block, six 21-bit fields (the low 21 bits of each word, then the
+// top 11 bits of words 0 and 1, and of words 2 and 3, joined)
 template <typename R>
-HD void gauss6_c2(const Stream& st, uint32_t phase, uint32_t v, R xi[6])
+HD void uniforms6_c2(const Stream& st, uint32_t phase, uint32_t v, R u[6])
 {
     const Words a = st.block(phase, v);
     const uint32_t m21 = 0x1FFFFFu;
-    const uint32_t f4 = (a.w[0] >> 21) | (((a.w[1] >> 21) & 0x3FFu) << 11);
-    const uint32_t f5 = (a.w[2] >> 21) | (((a.w[3] >> 21) & 0x3FFu) << 11);
-    box_muller<R>(unit21<R>(a.w[0] & m21), unit21<R>(a.w[1] & m21), &xi[0], &xi[1]);
-    box_muller<R>(unit21<R>(a.w[2] & m21), unit21<R>(a.w[3] & m21), &xi[2], &xi[3]);
-    box_muller<R>(unit21<R>(f4), unit21<R>(f5), &xi[4], &xi[5]);
+    u[0] = unit21<R>(a.w[0] & m21);
+    u[1] = unit21<R>(a.w[1] & m21);
+    u[2] = unit21<R>(a.w[2] & m21);
+    u[3] = unit21<R>(a.w[3] & m21);
+    u[4] = unit21<R>((a.w[0] >> 21) | (((a.w[1] >> 21) & 0x3FFu) << 11));
+    u[5] = unit21<R>((a.w[2] >> 21) | (((a.w[3] >> 21) & 0x3FFu) << 11));
+}
+
+// Gaussian 6-vector number v of a phase, contract 1: pairs (u0, u1), (u2, u3), (u4, u5)
+template <typename R>
+HD void gauss6_c1(const Stream& st, uint32_t phase, uint32_t v, R xi[6])
+{
+    R u[6];
+    uniforms6_c1<R>(st, phase, v, u);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) box_muller<R>(u[2 * j], u[2 * j + 1], &xi[2 * j], &xi[2 * j + 1]);
+}
+
+// Per-precision constants of the position update.
+template <typename R>
+struct StepScale {
+    R dt;    // time step
+    R sqdt;  // sqrt(dt): the increment of the +-1 walk
+    R rad;   // Box-Muller radius with sqrt(dt) folded in: sqrt(dt) sqrt(-2 ln u) = sqrt(rad logb(u))
+    R lim2;  // 2 a dt of the drift limiting (a = drift_limit; 0: none)
+};
+// binary32 takes the base-2 logarithm (v_log_f32), binary64 the natural one
+HD StepScale<float> step_scale(double dt, double drift_limit, float)
+{
+    return StepScale<float>{(float)dt, (float)std::sqrt(dt), (float)(-2.0 * 0.69314718055994531 * dt),
+                            (float)(2.0 * drift_limit * dt)};
+}
+HD StepScale<double> step_scale(double dt, double drift_limit, double)
+{
+    return StepScale<double>{dt, std::sqrt(dt), -2.0 * dt, 2.0 * drift_limit * dt};
+}
+
+// The increment sqrt(dt) xi of one step, as sqrt(dt) xi_k = r[k / 2] u[k]: for the
+// Gaussian noise a Box-Muller radius (sqrt(dt) included) and cos / sin of the angle,
+// for the +-1 walk sqrt(dt) and the signs.  Kept factored, the position update is one
+// fused multiply-add per coordinate.
+template <typename R>
+struct Increment {
+    R r[3];
+    R u[6];
+};
+
+template <typename R>
+HD void increment_from_uniforms(const R u[6], R rad, Increment<R>& inc)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        inc.r[j] = m::sqrt_(m::logb_(u[2 * j]) * rad);
+        m::sincos2pi(u[2 * j + 1], &inc.u[2 * j + 1], &inc.u[2 * j]);
+    }
 }
 
 // +-1 walk: step k uses bits 6 (k mod 5) + j of word (k mod 20) / 5 of block k / 20
@@ -216,18 +282,21 @@ HD void pm1_from_word(uint32_t word, uint32_t k, R xi[6])
     for (int j = 0; j < 6; ++j) xi[j] = ((word >> (sh + (uint32_t)j)) & 1u) ? (R)1 : (R)-1;
 }
 
-// The propagation noise of global step k for one walker.  The +-1 walk keeps
+// The propagation increment of global step k for one walker.  The +-1 walk keeps
 // the Philox block it is reading (one block serves 20 steps).
 template <typename R, int NOISE>
 struct NoiseGen {
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, blk = 0xFFFFFFFFu;
 
-    HD void draw(const Stream& st, uint32_t k, R xi[6])
+    HD void draw(const Stream& st, uint32_t k, const StepScale<R>& ss, Increment<R>& inc)
     {
-        if (NOISE == NOISE_G1) {
-            gauss6_c1<R>(st, PHASE_GAUSS, k, xi, nullptr);
-        } else if (NOISE == NOISE_G2) {
-            gauss6_c2<R>(st, PHASE_GAUSS, k, xi);
+        if (NOISE == NOISE_G1 || NOISE == NOISE_G2) {
+            R u[6];
+            if (NOISE == NOISE_G1)
+                uniforms6_c1<R>(st, PHASE_GAUSS, k, u);
+            else
+                uniforms6_c2<R>(st, PHASE_GAUSS, k, u);
+            increment_from_uniforms<R>(u, ss.rad, inc);
         } else {
             const uint32_t b = k / 20u;
             if (b != blk) {
@@ -240,7 +309,9 @@ struct NoiseGen {
             }
             const uint32_t wi = (k % 20u) / 5u;
             const uint32_t word = wi == 0 ? w0 : (wi == 1 ? w1 : (wi == 2 ? w2 : w3));
-            pm1_from_word<R>(word, k, xi);
+            pm1_from_word<R>(word, k, inc.u);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) inc.r[j] = ss.sqdt;
         }
     }
 };
@@ -326,11 +397,11 @@ HD void drift_from(const R y[6], const Geo<R>& g, R a1, R a2, R w, R b[6])
 // gphi2 (optional): |grad ln|Phi||^2 summed over both electrons, Phi the orbital
 // part (the factor that carries the node), for the node-distance estimate.
 template <typename R, int TRIAL>
-HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 = nullptr)
+HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 = nullptr)
 {
     Geo<R> g;
     geometry(y, g);
-    int sign = 1;
+    R node = (R)1;  // a value with the sign of psi (the orbital factor for the node trials)
     if (TRIAL == TRIAL_EXPO) {
         drift_from(y, g, -p.A * g.i1, -p.A * g.i2, (R)0, b);
         if (gphi2) *gphi2 = (R)2 * p.A * p.A;
@@ -382,7 +453,7 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2
         if (gphi2) *gphi2 = g1 * g1 + g2 * g2;
         const R cross = (g1 * g.p1 * g.i1 - g2 * g.p2 * g.i2) * g.i12;  // g1 h1.h12 - g2 h2.h12
         el = (R)-0.5 * (l1 + l2) - j.up * cross - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
-        sign = (D > (R)0) ? 1 : ((D < (R)0) ? -1 : 0);
+        node = D;
     } else if (TRIAL == TRIAL_PZ_SUM) {
         // Phi = (z1 + z2)(f + g) (trial function 7): with Zs = z1 + z2 and S = f + g,
         // grad_i Phi / Phi = zhat / Zs + gs_i h_i, gs_1 = -(A t1 + a t2) / (t1 + t2),
@@ -412,7 +483,7 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2
         // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12: the zhat / Zs terms cancel
         const R cr = (a1 * g.p1 - a2 * g.p2) * g.i12;
         el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
-        sign = (Zs > (R)0) ? 1 : ((Zs < (R)0) ? -1 : 0);
+        node = Zs;
     } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
@@ -439,9 +510,9 @@ HD int trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2
         // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12
         const R cr = (a1 * g.p1 - a2 * g.p2 + (s1 - s2) * g.D[2]) * g.i12;
         el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
-        sign = (P > (R)0) ? 1 : ((P < (R)0) ? -1 : 0);
+        node = P;
     }
-    return sign;
+    return node;
 }
 
 // V = -Z/r1 - Z/r2 + ee/r12 (the integrand of the plain walk)
@@ -491,7 +562,7 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
                     double sigma_m, double y[6])
 {
     double xi[6];
-    gauss6_c1<double>(st, PHASE_INIT, 0u, xi, nullptr);
+    gauss6_c1<double>(st, PHASE_INIT, 0u, xi);
 #pragma unroll
     for (int k = 0; k < 6; ++k) y[k] = init_sigma * xi[k];
     double lp = trial_lnpsi<TRIAL>(tp, y);
@@ -520,53 +591,85 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
 template <typename R>
 struct WalkerState {
     R y[6];
-    R b[6];     // drift used by the next step (limited when drift_limit > 0; 0 for the plain walk)
+    R b[6];     // drift grad ln|psi| at y
+    R bdt;      // its factor in the next position update: dt (times the limiting factor; 0 for the plain walk)
     R el;       // local energy at y
     double eb;  // integrand at y: E_L - e_ref (limited when drift_limit > 0), or V - e_ref (plain walk)
     R gn2;      // |grad ln|Phi||^2 at y (node-touch estimate)
-    int sign;
+    R sgn;  // sign of psi at y: +-1, or 0 on the node
     double lnw;
 };
 
 struct StepConst {
-    double dt, half_dt, e_ref;
+    double dt, e_ref;
     int quad_right;
+    // quadrature of ln w over a step: ln w -= quad_c (quad_prev eb + en); (dt/2)(eb + en)
+    // for the trapezoid, dt en for the right end-point
+    double quad_c, quad_prev;
     double limit_adt;  // drift_limit * dt (0: no limiting)
     int plain;         // plain Feynman-Kac walk: no drift, integrand V - e_ref
     int bridge;        // weight each step by the chance that its path missed the node
     double two_over_dt;
+    double lnw_absorbed;  // -inf, held here so that the step's test reads it from a scalar register
 };
 
+inline StepConst make_step_const(double dt, double e_ref, bool quad_right, double drift_limit, bool plain,
+                                 bool bridge)
+{
+    StepConst sc;
+    sc.dt = dt;
+    sc.e_ref = e_ref;
+    sc.quad_right = quad_right ? 1 : 0;
+    sc.quad_c = quad_right ? dt : 0.5 * dt;
+    sc.quad_prev = quad_right ? 0.0 : 1.0;
+    sc.limit_adt = drift_limit * dt;
+    sc.plain = plain ? 1 : 0;
+    sc.bridge = bridge ? 1 : 0;
+    sc.two_over_dt = 2.0 / dt;
+    sc.lnw_absorbed = -INFINITY;
+    return sc;
+}
+
+// ln w = -inf marks an absorbed walker (one v_cmp_class on the device)
+HD bool absorbed(double lnw)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_class(lnw, 4);  // class bit 2: negative infinity
+#else
+    return lnw == -INFINITY;
+#endif
+}
+
 // Drift / integrand limiting near singular points: f = 2 / (1 + sqrt(1 + 2 a dt |b|^2)),
-// b -> f b, E_L - e_ref -> f (E_L - e_ref).
+// b -> f b, E_L - e_ref -> f (E_L - e_ref).  The limited drift is carried as the step
+// factor bdt = dt f of the unlimited one: the position update takes Y + bdt b.
 template <typename R>
-HD double limit_drift(const StepConst& sc, R b[6], R el)
+HD double limit_drift(const StepConst& sc, const StepScale<R>& ss, const R b[6], R el, R& bdt)
 {
     double e = (double)el - sc.e_ref;
+    bdt = ss.dt;
     if (sc.limit_adt > 0.0) {
         R v2 = 0;
 #pragma unroll
         for (int k = 0; k < 6; ++k) v2 += b[k] * b[k];
-        const R x2 = (R)(2.0 * sc.limit_adt) * v2;
-        const R f = (R)2 * m::rcp_((R)1 + m::sqrt_((R)1 + x2));
-#pragma unroll
-        for (int k = 0; k < 6; ++k) b[k] *= f;
+        const R f = (R)2 * m::rcp_((R)1 + m::sqrt_((R)1 + ss.lim2 * v2));
+        bdt = ss.dt * f;
         e *= (double)f;
     }
     return e;
 }
 
-// Integrand at y, and the drift the next step uses.  EXT kernels read the variant
-// flags at run time; the others are the generalized walk only.
+// Integrand at y, and the drift step factor of the next step.  EXT kernels read the
+// variant flags at run time; the others are the generalized walk only.
 template <typename R, bool EXT>
-HD double integrand(const TrialParams<R>& tp, const StepConst& sc, const R y[6], R b[6], R el)
+HD double integrand(const TrialParams<R>& tp, const StepConst& sc, const StepScale<R>& ss, const R y[6], const R b[6], R el,
+                    R& bdt)
 {
     if (EXT && sc.plain) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) b[k] = (R)0;
+        bdt = (R)0;  // no drift
         return (double)potential<R>(tp, y) - sc.e_ref;
     }
-    return limit_drift<R>(sc, b, el);
+    return limit_drift<R>(sc, ss, b, el, bdt);
 }
 
 // ln of the chance that a Brownian bridge over one step, between points at node
@@ -579,45 +682,35 @@ HD double bridge_log_survival(const StepConst& sc, double ga, double gb)
 }
 
 template <typename R, int TRIAL, bool EXT = false>
-HD void walker_reset(const TrialParams<R>& tp, const StepConst& sc, WalkerState<R>& w)
+HD void walker_reset(const TrialParams<R>& tp, const StepConst& sc, const StepScale<R>& ss, WalkerState<R>& w)
 {
-    w.sign = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el, EXT ? &w.gn2 : nullptr);
-    w.eb = integrand<R, EXT>(tp, sc, w.y, w.b, w.el);
+    const R nd = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el, EXT ? &w.gn2 : nullptr);
+    w.sgn = (nd > (R)0) ? (R)1 : ((nd < (R)0) ? (R)-1 : (R)0);
+    w.eb = integrand<R, EXT>(tp, sc, ss, w.y, w.b, w.el, w.bdt);
 }
 
-// Y' = Y + dt b + sqrt(dt) xi; node crossing absorbs (lnw = -inf, frozen);
-// otherwise the quadrature updates ln w in binary64.
+// Y' = Y + dt b + sqrt(dt) xi, ln w updated by the quadrature in binary64.  A step
+// that crosses the node absorbs the walker: it keeps Y' (where it was found across the
+// node) with ln w = -inf, and takes no further steps.
 template <typename R, int TRIAL, bool EXT = false>
-HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, R dt_r, R sqdt_r, const R xi[6],
+HD void walker_step(const TrialParams<R>& tp, const StepConst& sc, const StepScale<R>& ss, const Increment<R>& inc,
                     WalkerState<R>& w)
 {
-    if (w.lnw == -INFINITY) return;
-    R yt[6], bt[6], elt, gt = (R)0;
+    if (w.lnw == sc.lnw_absorbed) return;  // absorbed
 #pragma unroll
-    for (int k = 0; k < 6; ++k) yt[k] = w.y[k] + dt_r * w.b[k] + sqdt_r * xi[k];
-    const int st = trial_eval<R, TRIAL>(tp, yt, bt, elt, EXT ? &gt : nullptr);
-    if (has_node<TRIAL>::value && (st != w.sign || st == 0)) {
-        w.lnw = -INFINITY;
-        return;
-    }
-    const double en = integrand<R, EXT>(tp, sc, yt, bt, elt);
-    double lw;
-    if (sc.quad_right)
-        lw = w.lnw - sc.dt * en;
-    else
-        lw = w.lnw - sc.half_dt * (w.eb + en);
+    for (int k = 0; k < 6; ++k) w.y[k] = m::fma_(inc.r[k >> 1], inc.u[k], m::fma_(w.bdt, w.b[k], w.y[k]));
+    R gt = (R)0;
+    const R nd = trial_eval<R, TRIAL>(tp, w.y, w.b, w.el, EXT ? &gt : nullptr);
+    const double en = integrand<R, EXT>(tp, sc, ss, w.y, w.b, w.el, w.bdt);
+    double lw = m::fma_(-sc.quad_c, m::fma_(sc.quad_prev, w.eb, en), w.lnw);
     if (EXT && has_node<TRIAL>::value && sc.bridge) lw += bridge_log_survival(sc, (double)w.gn2, (double)gt);
-    if (!__builtin_isfinite((double)elt)) lw = NAN;
+    lw = m::fma_(0.0, (double)w.el, lw);  // NaN when E_L is not finite
+    // node crossing: psi(Y') is zero, NaN or of the other sign (or the walk started on the node)
+    if (has_node<TRIAL>::value && !(nd * w.sgn > (R)0)) lw = -INFINITY;
     w.lnw = lw;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        w.y[k] = yt[k];
-        w.b[k] = bt[k];
-    }
-    w.el = elt;
     w.eb = en;
     w.gn2 = gt;
-    w.sign = st;
+    w.sgn = m::copysign_((R)1, nd);
 }
 
 }  // namespace hefk

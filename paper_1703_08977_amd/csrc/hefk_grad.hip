@@ -26,7 +26,7 @@ constexpr int kGradBlock = 256;
 struct GArgs {
     TrialParams<double> tp;
     StepConst sc;
-    double dt, sqdt;
+    StepScale<double> ss;
     uint32_t key0, key1;
     uint64_t walker_offset;
     int64_t n;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kGradBlock) void grad_kernel(const GArgs a)
         DeviceTape tape{a.ckpt, a.tape, a.n, i};
         SampleView sv{a.samples, a.g, a.g2};
         double P = 0.0, Q = 0.0;
-        walker_reverse<TRIAL, NOISE>(a.tp, a.sc, a.dt, a.sqdt, st, a.n_steps, a.sample_every, a.ckpt_every, sv,
+        walker_reverse<TRIAL, NOISE>(a.tp, a.sc, a.ss, st, a.n_steps, a.sample_every, a.ckpt_every, sv,
                                      tape, gth, &P, &Q);
         if (a.score) {
             double y0[6], l0, sc[2];
@@ -229,13 +229,8 @@ extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const doubl
     a.tp.ee = (double)p->ee;
     a.tp.sym = 1.0;
     a.tp.r0 = 0.0;
-    a.sc.dt = p->dt;
-    a.sc.half_dt = 0.5 * p->dt;
-    a.sc.e_ref = p->e_ref;
-    a.sc.quad_right = (p->quad == HE_FK_QUAD_RIGHT);
-    a.sc.limit_adt = 0.0;
-    a.dt = p->dt;
-    a.sqdt = std::sqrt(p->dt);
+    a.sc = make_step_const(p->dt, p->e_ref, p->quad == HE_FK_QUAD_RIGHT, 0.0, false, false);
+    a.ss = step_scale(p->dt, 0.0, 0.0);
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
     a.walker_offset = p->walker_offset;

@@ -29,8 +29,8 @@ struct KArgs {
     TrialParams<double> tpd;
     TrialParams<float> tpf;
     StepConst sc;
-    double dt, sqdt;
-    float dtf, sqdtf;
+    StepScale<double> ssd;
+    StepScale<float> ssf;
     double init_sigma, metropolis_sigma;
     uint32_t key0, key1;
     uint64_t walker_offset;
@@ -55,6 +55,19 @@ template <>
 __device__ __forceinline__ const TrialParams<float>& tparams<float>(const KArgs& a)
 {
     return a.tpf;
+}
+
+template <typename R>
+__device__ __forceinline__ const StepScale<R>& sscale(const KArgs& a);
+template <>
+__device__ __forceinline__ const StepScale<double>& sscale<double>(const KArgs& a)
+{
+    return a.ssd;
+}
+template <>
+__device__ __forceinline__ const StepScale<float>& sscale<float>(const KArgs& a)
+{
+    return a.ssf;
 }
 
 __device__ __forceinline__ Stream make_stream(const KArgs& a, int64_t i)
@@ -115,8 +128,7 @@ __global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVE
 {
     __shared__ double red[kRedSlots];
     const TrialParams<R>& tp = tparams<R>(a);
-    const R dt_r = (sizeof(R) == 8) ? (R)a.dt : (R)a.dtf;
-    const R sqdt_r = (sizeof(R) == 8) ? (R)a.sqdt : (R)a.sqdtf;
+    const StepScale<R>& ss = sscale<R>(a);
     const int64_t n = a.n;
     const int64_t n_chunks = (n + kBlock - 1) / kBlock;
     double* part = a.partials + (size_t)blockIdx.x * (size_t)a.n_samples * 8;
@@ -132,7 +144,7 @@ __global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVE
 #pragma unroll
         for (int k = 0; k < 6; ++k) w.y[k] = x[(int64_t)k * n + ii];
         w.lnw = a.lnw[ii];
-        walker_reset<R, TRIAL, EXT>(tp, a.sc, w);
+        walker_reset<R, TRIAL, EXT>(tp, a.sc, ss, w);
 
         sample_row<R>(a, part, first, valid, w, red);
         if (a.ckpt && valid) {
@@ -144,9 +156,9 @@ __global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVE
         int row = 1, until_sample = a.sample_every, until_ckpt = a.ckpt_every, crow = 1;
         NoiseGen<R, NOISE> noise;
         for (int k = 0; k < a.n_steps; ++k) {
-            R xi[6];
-            noise.draw(st, (uint32_t)(a.step0 + k), xi);
-            walker_step<R, TRIAL, EXT>(tp, a.sc, dt_r, sqdt_r, xi, w);
+            Increment<R> inc;
+            noise.draw(st, (uint32_t)(a.step0 + k), ss, inc);
+            walker_step<R, TRIAL, EXT>(tp, a.sc, ss, inc, w);
             if (--until_sample == 0) {
                 until_sample = a.sample_every;
                 sample_row<R>(a, part + (size_t)row * 8, first, valid, w, red);
@@ -304,18 +316,10 @@ static KArgs make_args(const he_fk_params* p)
     a.tpf.Z = (float)a.tpd.Z;
     a.tpf.ee = (float)a.tpd.ee;
     a.tpf.sym = (float)a.tpd.sym;
-    a.sc.dt = p->dt;
-    a.sc.half_dt = 0.5 * p->dt;
-    a.sc.e_ref = p->e_ref;
-    a.sc.quad_right = (p->quad == HE_FK_QUAD_RIGHT);
-    a.sc.limit_adt = p->drift_limit * p->dt;
-    a.sc.plain = (p->flags & HE_FK_FLAG_PLAIN) != 0;
-    a.sc.bridge = (p->flags & HE_FK_FLAG_BRIDGE) != 0;
-    a.sc.two_over_dt = 2.0 / p->dt;
-    a.dt = p->dt;
-    a.sqdt = std::sqrt(p->dt);
-    a.dtf = (float)p->dt;
-    a.sqdtf = (float)std::sqrt(p->dt);
+    a.sc = make_step_const(p->dt, p->e_ref, p->quad == HE_FK_QUAD_RIGHT, p->drift_limit,
+                           (p->flags & HE_FK_FLAG_PLAIN) != 0, (p->flags & HE_FK_FLAG_BRIDGE) != 0);
+    a.ssd = step_scale(p->dt, p->drift_limit, 0.0);
+    a.ssf = step_scale(p->dt, p->drift_limit, 0.0f);
     a.init_sigma = p->init_sigma;
     a.metropolis_sigma = p->metropolis_sigma;
     a.key0 = (uint32_t)p->seed;

@@ -9,11 +9,12 @@
 namespace hefk {
 
 template <int TRIAL, int NOISE, class Samples, class Tape>
-HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, double dt, double sqdt, const Stream& st,
+HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, const StepScale<double>& ss, const Stream& st,
                        int n_steps, int sample_every, int ckpt_every, const Samples& sv, Tape& tape, double gth[2],
                        double* p_total, double* q_total)
 {
     const bool right = sc.quad_right != 0;
+    const double dt = ss.dt;
     const int n_seg = n_steps / ckpt_every;
     double lam[6] = {0, 0, 0, 0, 0, 0};
     double P = 0.0, Q = 0.0;
@@ -22,13 +23,13 @@ HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, doubl
         // recompute the segment from its checkpoint (same arithmetic as the forward kernel)
         WalkerState<double> w;
         tape.load_ckpt(seg, w.y, w.lnw);
-        walker_reset<double, TRIAL>(tp, sc, w);
+        walker_reset<double, TRIAL>(tp, sc, ss, w);
         tape.put(0, w.y, w.lnw);
         NoiseGen<double, NOISE> noise;
         for (int k = 0; k < ckpt_every; ++k) {
-            double xi[6];
-            noise.draw(st, (uint32_t)(k0 + k), xi);
-            walker_step<double, TRIAL>(tp, sc, dt, sqdt, xi, w);
+            Increment<double> inc;
+            noise.draw(st, (uint32_t)(k0 + k), ss, inc);
+            walker_step<double, TRIAL>(tp, sc, ss, inc, w);
             tape.put(k + 1, w.y, w.lnw);
         }
         // reverse over the steps of the segment (step k0 belongs to the segment below, except k0 = 0)

@@ -27,11 +27,14 @@ from __future__ import annotations
 
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 39.32e12
 
+NODE_TRIALS = ("triplet", "triplet_r0", "pz", "pz_sum")
+
 # Philox4x32-10 block per step: 10 rounds x (two 32x32->64 multiplies, two three-input
-# xors), less the work that depends only on the walker id, the phase and the key (round 1
-# and the first multiply of round 2, computed once per walker); the key schedule runs on
-# the scalar unit.
-PHILOX_BLOCK = 9 * (2 + 2) - 1
+# xors), less the work fixed per walker or uniform over the wave: round 1 multiplies the
+# block index (the step, a scalar) and the walker id (fixed), so it needs only the xor
+# that joins them; round 2's product of the fixed word is fixed too.  The key schedule
+# runs on the scalar unit.
+PHILOX_BLOCK = 10 * (2 + 2) - 3 - 1
 
 # (main-pipe operations, transcendental instructions) per function
 F32 = {"sqrt": (0, 1), "rcp": (0, 1), "exp": (1, 1), "expm1": (9, 1), "log": (1, 1), "sincos": (0, 2)}
@@ -56,14 +59,17 @@ def _noise(c: _Count, f, noise: str, contract: int):
     if noise == "pm1":
         c.ops(PHILOX_BLOCK / 20.0 + 6 * 2)  # one block per 20 steps; bit extract + select per coordinate
         return
-    # Box-Muller per pair: -2 log u1, sqrt, sin and cos of 2 pi u2, two products
+    # Box-Muller per pair: the radius sqrt(dt) sqrt(-2 ln u1) as the square root of a scaled
+    # logarithm, sin and cos of 2 pi u2; the radius-times-cosine products are the
+    # multiplies of the Euler step's fused multiply-adds
     for _ in range(3):
         c.fn(f, "log")
         c.fn(f, "sqrt")
         c.fn(f, "sincos")
-        c.ops(2)
     if contract == 2:
-        c.ops(PHILOX_BLOCK + 14 + 6 * 2)  # one block, 21-bit field extraction, convert + scale
+        # one block; the six 21-bit fields: four masks, and a shift, a shift and a
+        # shift-and-or for each of the two joined fields; convert + scale each
+        c.ops(PHILOX_BLOCK + 4 + 2 * 3 + 6 * 2)
     else:
         c.ops(2 * PHILOX_BLOCK + 6 * 2)  # two blocks; funnel shift + add (binary32), convert + scale (binary64)
 
@@ -93,25 +99,25 @@ def _trial(c: _Count, f, trial: str):
         c.fn(f, "expm1")
         c.fn(f, "rcp")
         # e = 1 + em, D (2), g1, g2 (2 x 3), Laplacian ratios (2 x 6), g_i / r_i (2), w (1), drift,
-        # cross term (5), E_L (8), sign (3)
-        c.ops(1 + 2 + 6 + 12 + 2 + 1 + drift + 5 + 8 + 3)
+        # cross term (5), E_L (8)
+        c.ops(1 + 2 + 6 + 12 + 2 + 1 + drift + 5 + 8)
         return
     c.fn(f, "exp")
     c.fn(f, "rcp")
     if trial == "triplet_r0":
         # q_i = r0 - r_i, u_i = 1 + A q_i (4), D (2), g1, g2 (2 x 4), Laplacian ratios (2 x 8),
-        # g_i / r_i (2), w (1), drift, cross term (5), E_L (8), sign (3)
-        c.ops(4 + 2 + 8 + 16 + 2 + 1 + drift + 5 + 8 + 3)
+        # g_i / r_i (2), w (1), drift, cross term (5), E_L (8)
+        c.ops(4 + 2 + 8 + 16 + 2 + 1 + drift + 5 + 8)
         return
     if trial == "pz_sum":
         c.fn(f, "rcp")  # 1 / (z1 + z2)
         # t1 + t2 (1), z1 + z2 (1), g1, g2 (2 x 3), a_i (2), w (1), drift, z terms (2), node-gradient
-        # Laplacian ratios (2 x 8), cross term (3), E_L (8), sign (3)
-        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 16 + 3 + 8 + 3)
+        # Laplacian ratios (2 x 8), cross term (3), E_L (8)
+        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 16 + 3 + 8)
         return
     # P_z: sym t2 (1), P (2), k1, k2 (2 x 4), a1, a2 (2 x 2), s1, s2 (2), w (1), drift, z terms (2),
-    # Laplacian ratios (2 x 7), cross term (5), E_L (8), sign (3)
-    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 14 + 5 + 8 + 3)
+    # Laplacian ratios (2 x 7), cross term (5), E_L (8)
+    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 14 + 5 + 8)
 
 
 def count(cfg: dict) -> _Count:
@@ -120,13 +126,19 @@ def count(cfg: dict) -> _Count:
     c = _Count()
     _noise(c, f, cfg.get("noise", "gauss"), int(cfg.get("contract", 1)))
     _trial(c, f, cfg["trial"])
-    c.ops(12)  # Euler step
+    c.ops(12)  # Euler step: Y + (dt f) b, then + r u, one fused multiply-add each per coordinate
     if cfg.get("drift_limit", 0.0) > 0:
-        c.ops(6 + 1 + 1 + 1 + 1 + 6 + 1)  # |b|^2, 2 a dt |b|^2, 1 + ., 1 + sqrt, 2 / ., scale b, scale e
+        # |b|^2, 2 a dt |b|^2, 1 + ., 1 + sqrt, 2 / ., the drift's step factor dt f (the
+        # limited drift f b enters the next Euler step as (dt f) b), scale e (conversion + product)
+        c.ops(6 + 1 + 1 + 1 + 1 + 1 + 2)
         c.fn(f, "sqrt")
         c.fn(f, "rcp")
-    c.ops(6)  # node test and state commit
-    c.ops(6)  # ln w update in binary64 (conversion, shift by e_ref, quadrature, NaN guard)
+    c.ops(1)  # the absorbed-walker test
+    if cfg["trial"] in NODE_TRIALS:
+        # product of the orbital factor with the old sign and its test, the new sign
+        # (copysign), ln w = -inf on a crossing (two 32-bit selects)
+        c.ops(2 + 1 + 2)
+    c.ops(5)  # ln w update in binary64: conversion, shift by e_ref, quadrature (2), NaN guard
     return c
 
 

@@ -53,7 +53,8 @@ void one(const TrialParams<double>& tp, const StepConst& sc, int n_met, double m
     WalkerState<double> w;
     init_walker<TRIAL>(tp, st, n_met, isig, msig, w.y);
     w.lnw = 0.0;
-    walker_reset<double, TRIAL>(tp, sc, w);
+    const StepScale<double> ss = step_scale(sc.dt, 0.0, 0.0);
+    walker_reset<double, TRIAL>(tp, sc, ss, w);
     HostTape tape;
     tape.ck.assign(7 * (n_steps / ce + 1), 0.0);
     tape.tp.assign(7 * (ce + 1), 0.0);
@@ -63,15 +64,14 @@ void one(const TrialParams<double>& tp, const StepConst& sc, int n_met, double m
     };
     save(0);
     NoiseGen<double, NOISE> noise;
-    const double dt = sc.dt, sq = std::sqrt(sc.dt);
     for (int k = 0; k < n_steps; ++k) {
-        double xi[6];
-        noise.draw(st, (uint32_t)k, xi);
-        walker_step<double, TRIAL>(tp, sc, dt, sq, xi, w);
+        Increment<double> inc;
+        noise.draw(st, (uint32_t)k, ss, inc);
+        walker_step<double, TRIAL>(tp, sc, ss, inc, w);
         if ((k + 1) % ce == 0) save((k + 1) / ce);
     }
     double gth[2] = {0, 0}, P = 0, Q = 0;
-    walker_reverse<TRIAL, NOISE>(tp, sc, dt, sq, st, n_steps, se, ce, hs, tape, gth, &P, &Q);
+    walker_reverse<TRIAL, NOISE>(tp, sc, ss, st, n_steps, se, ce, hs, tape, gth, &P, &Q);
     std::printf("%.17g %.17g %.17g %.17g\n", gth[0], gth[1], P, Q);
 }
 
@@ -97,7 +97,7 @@ int main()
         hs.g2_.push_back(e);
     }
     TrialParams<double> tp{th[0], th[1], th[2], th[3], Z, (double)ee, 1.0, 0.0};
-    StepConst sc{dt, 0.5 * dt, e_ref, quad, 0.0};
+    const StepConst sc = make_step_const(dt, e_ref, quad != 0, 0.0, false, false);
     long n;
     if (std::scanf("%ld", &n) != 1) return 2;
     for (long i = 0; i < n; ++i) {

@@ -51,25 +51,18 @@ void run_walker(const Cfg& c, unsigned long long g)
     WalkerState<R> w;
     for (int k = 0; k < 6; ++k) w.y[k] = (R)y0[k];
     w.lnw = 0.0;
-    StepConst sc;
-    sc.dt = c.dt;
-    sc.half_dt = 0.5 * c.dt;
-    sc.e_ref = c.e_ref;
-    sc.quad_right = c.quad == 1;
-    sc.limit_adt = c.limit * c.dt;
-    sc.plain = (c.flags & 1) != 0;
-    sc.bridge = (c.flags & 2) != 0;
-    sc.two_over_dt = 2.0 / c.dt;
-    walker_reset<R, TRIAL, EXT>(tp, sc, w);
-    const R dt_r = (R)c.dt, sqdt_r = (R)std::sqrt(c.dt);
+    const StepConst sc =
+        make_step_const(c.dt, c.e_ref, c.quad == 1, c.limit, (c.flags & 1) != 0, (c.flags & 2) != 0);
+    const StepScale<R> ss = step_scale(c.dt, c.limit, R());
+    walker_reset<R, TRIAL, EXT>(tp, sc, ss, w);
     std::vector<double> ell, els;
     ell.push_back(w.lnw);
     els.push_back((double)w.el);
     NoiseGen<R, NOISE> noise;
     for (long k = 0; k < c.n_steps; ++k) {
-        R xi[6];
-        noise.draw(st, (uint32_t)k, xi);
-        walker_step<R, TRIAL, EXT>(tp, sc, dt_r, sqdt_r, xi, w);
+        Increment<R> inc;
+        noise.draw(st, (uint32_t)k, ss, inc);
+        walker_step<R, TRIAL, EXT>(tp, sc, ss, inc, w);
         if ((k + 1) % c.sample_every == 0) {
             ell.push_back(w.lnw);
             els.push_back((double)w.el);
