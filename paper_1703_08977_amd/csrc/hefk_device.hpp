@@ -39,14 +39,17 @@ HD double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 HD double copysign_(double a, double b) { return __builtin_copysign(a, b); }
 HD float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
 HD float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-HD double sqrt_(double x) { return f64::sqrt(x); }
-HD double rcp_(double x) { return f64::rcp(x); }
+// The step's binary64 square roots and reciprocals take arguments that are not zero
+// (distances, 1 + ..., the node factor off the node, the Box-Muller radicand), and its
+// logarithms uniforms of the noise: the forms without the zero and subnormal tests.
+HD double sqrt_(double x) { return f64::sqrt_pos(x); }
+HD double rcp_(double x) { return f64::rcp_nz(x); }
 HD double exp_(double x) { return f64::exp(x); }
 HD double expm1_(double x) { return ::expm1(x); }
 HD double log_(double x) { return f64::log(x); }
 HD double neg2log_(double x) { return f64::neg2log(x); }
 // the logarithm whose base the Box-Muller radius scale assumes: natural in binary64
-HD double logb_(double x) { return f64::log(x); }
+HD double logb_(double x) { return f64::log_normal(x); }
 // sin(2 pi u), cos(2 pi u) for u in (0, 1)
 HD void sincos2pi(double u, double* s, double* c) { f64::sincos2pi(u, s, c); }
 
@@ -160,6 +163,18 @@ struct Stream {
     uint32_t k0, k1;  // key: the seed
     uint32_t g0, g1;  // counter words 2, 3: the global walker id
     HD Words block(uint32_t phase, uint32_t b) const { return philox(b, phase, g0, g1, k0, k1); }
+    // The same stream with a key the compiler must take as unknown at each call
+    // (device): the round keys are then bumped on the scalar unit per block instead of
+    // being hoisted out of the step loop, where the binary64 step has no scalar
+    // registers left to hold all twenty of them.
+    HD Stream key_per_call() const
+    {
+        Stream s = *this;
+#if defined(__HIP_DEVICE_COMPILE__)
+        asm volatile("" : "+s"(s.k0), "+s"(s.k1));
+#endif
+        return s;
+    }
 };
 
 // uniform (0,1) from a 32-bit word: binary64 (w + 1/2) 2^-32; binary32 from the top 23
@@ -288,8 +303,9 @@ template <typename R, int NOISE>
 struct NoiseGen {
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, blk = 0xFFFFFFFFu;
 
-    HD void draw(const Stream& st, uint32_t k, const StepScale<R>& ss, Increment<R>& inc)
+    HD void draw(const Stream& st_in, uint32_t k, const StepScale<R>& ss, Increment<R>& inc)
     {
+        const Stream st = (sizeof(R) == 8) ? st_in.key_per_call() : st_in;
         if (NOISE == NOISE_G1 || NOISE == NOISE_G2) {
             R u[6];
             if (NOISE == NOISE_G1)

@@ -11,6 +11,11 @@
 //   sqrt(x)     x >= 0: y ~ 1/sqrt(x) from the hardware seed, two Newton steps on
 //               g = x y, h = y/2 (Goldschmidt's coupled iteration), x = 0 -> 0.
 //   1/x         hardware reciprocal seed and two Newton steps, x = 0 -> inf.
+// sqrt_pos, rcp_nz and log_normal are the same arithmetic without the tests for
+// zero and subnormal arguments: the walker step calls them where its arguments
+// cannot be zero (a uniform of the noise, 1 + ..., a distance), and an argument
+// that is zero after all (an electron exactly on the nucleus) gives NaN there,
+// which marks the walker non-finite as the infinity of the tested form would.
 // Each is within a few units in the last place of the correctly rounded value over
 // those arguments.  Host builds use the same code (seeds from the C library).
 #pragma once
@@ -57,19 +62,27 @@ HD double rsq_seed(double x)
 #endif
 }
 
-// 1/x: seed and two Newton steps r <- r + r (1 - x r)
-HD double rcp(double x)
+// 1/x for finite x != 0: seed and two Newton steps r <- r + r (1 - x r)
+// (x = 0 gives NaN: the form for arguments that cannot be zero)
+HD double rcp_nz(double x)
 {
     double r = rcp_seed(x);
     double e = ::fma(-x, r, 1.0);
     r = ::fma(r, e, r);
     e = ::fma(-x, r, 1.0);
     r = ::fma(r, e, r);
-    return x == 0.0 ? from_bits(bits(x) | 0x7FF0000000000000ull) : r;  // +-inf for +-0
+    return r;
 }
 
-// sqrt(x), x >= 0
-HD double sqrt(double x)
+// 1/x, x = +-0 -> +-inf
+HD double rcp(double x)
+{
+    const double r = rcp_nz(x);
+    return x == 0.0 ? from_bits(bits(x) | 0x7FF0000000000000ull) : r;
+}
+
+// sqrt(x) for finite x > 0 (x = 0 gives NaN: the form for arguments that cannot be zero)
+HD double sqrt_pos(double x)
 {
     const double y = rsq_seed(x);
     double g = x * y, h = 0.5 * y;
@@ -78,21 +91,27 @@ HD double sqrt(double x)
     h = ::fma(h, r, h);
     const double d = ::fma(-g, g, x);
     g = ::fma(d, h, g);
+    return g;
+}
+
+// sqrt(x), x >= 0
+HD double sqrt(double x)
+{
+    const double g = sqrt_pos(x);
     return x == 0.0 ? 0.0 : g;
 }
 
-// log(x), x > 0 finite (0 -> -inf); arguments below 2^-1000 are scaled by 2^100 first
-HD double log(double x)
+// log(x) - e_off ln 2 for finite x >= 2^-1000 (the exponent offset enters before the
+// split multiplication by ln 2)
+HD double log_scaled(double x, double e_off)
 {
-    const bool tiny = x < 0x1p-1000;
-    const double xs = tiny ? x * 0x1p100 : x;
-    const uint64_t b = bits(xs);
+    const uint64_t b = bits(x);
     int e = (int)((b >> 52) & 0x7FF) - 1023;
     double m = from_bits((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull);  // [1, 2)
     const bool big = m > 1.4142135623730951;
     m = big ? 0.5 * m : m;
     e = big ? e + 1 : e;
-    const double s = (m - 1.0) * rcp(m + 1.0);
+    const double s = (m - 1.0) * rcp_nz(m + 1.0);
     const double z = s * s;
     // sum_{k=0}^{11} z^k / (2k + 1)
     double p = 1.0 / 23.0;
@@ -109,13 +128,24 @@ HD double log(double x)
     const double lm = 2.0 * s + 2.0 * s * z * p;  // 2 s (1 + z p), the leading term kept apart
     const double ln2_hi = 6.93147180369123816490e-01;  // ln 2 split: high part has 21 trailing zero bits
     const double ln2_lo = 1.90821492927058770002e-10;
-    const double fe = (double)e - (tiny ? 100.0 : 0.0);
-    const double r = fe * ln2_hi + (lm + fe * ln2_lo);
+    const double fe = (double)e - e_off;
+    return fe * ln2_hi + (lm + fe * ln2_lo);
+}
+
+// log(x) for finite x >= 2^-1000 (the form for arguments bounded away from zero and
+// from the subnormal range, such as the uniforms of the noise)
+HD double log_normal(double x) { return log_scaled(x, 0.0); }
+
+// log(x), x > 0 finite (0 -> -inf); arguments below 2^-1000 are scaled by 2^100 first
+HD double log(double x)
+{
+    const bool tiny = x < 0x1p-1000;
+    const double r = log_scaled(tiny ? x * 0x1p100 : x, tiny ? 100.0 : 0.0);
     return x == 0.0 ? -INFINITY : r;
 }
 
-// -2 log(x) for the Box-Muller radius
-HD double neg2log(double x) { return -2.0 * log(x); }
+// -2 log(u) for the Box-Muller radius, u a uniform of the noise (u >= 2^-33)
+HD double neg2log(double u) { return -2.0 * log_normal(u); }
 
 // sin(2 pi u), cos(2 pi u) for u in [0, 1)
 HD void sincos2pi(double u, double* s_out, double* c_out)
