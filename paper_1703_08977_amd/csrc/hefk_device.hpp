@@ -45,11 +45,17 @@ HD float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 HD double sqrt_(double x) { return f64::sqrt_pos(x); }
 HD double rcp_(double x) { return f64::rcp_nz(x); }
 HD double exp_(double x) { return f64::exp(x); }
-HD double expm1_(double x) { return ::expm1(x); }
+HD double expm1_(double x) { return f64::expm1_neg(x); }  // x <= 0
 HD double log_(double x) { return f64::log(x); }
 HD double neg2log_(double x) { return f64::neg2log(x); }
 // the logarithm whose base the Box-Muller radius scale assumes: natural in binary64
 HD double logb_(double x) { return f64::log_normal(x); }
+// r = sqrt(q) and 1/r of a squared distance q > 0
+HD void dist_inv(double q, double& r, double& i)
+{
+    r = f64::sqrt_pos(q);
+    i = f64::rcp_nz(r);
+}
 // sin(2 pi u), cos(2 pi u) for u in (0, 1)
 HD void sincos2pi(double u, double* s, double* c) { f64::sincos2pi(u, s, c); }
 
@@ -77,7 +83,25 @@ HD float exp_(float x)
     return ::expf(x);
 #endif
 }
-HD float expm1_(float x) { return ::expm1f(x); }
+// e^x - 1 for x <= 0 (the node factor of the triplet): for x > -0.35 the Taylor
+// series to x^7 (truncation below 2e-8 relative), else e^x - 1 from the hardware
+// exponential, which has no cancellation there (e^x < 0.71)
+HD float expm1_(float x)
+{
+    float q = (float)(1.0 / 5040.0);
+    q = m::fma_(q, x, (float)(1.0 / 720.0));
+    q = m::fma_(q, x, (float)(1.0 / 120.0));
+    q = m::fma_(q, x, (float)(1.0 / 24.0));
+    q = m::fma_(q, x, (float)(1.0 / 6.0));
+    q = m::fma_(q, x, 0.5f);
+    const float series = m::fma_(x * x, q, x);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float e = __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+#else
+    const float e = ::exp2f(x * 1.4426950408889634f);
+#endif
+    return x > -0.35f ? series : e - 1.0f;
+}
 HD float log_(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -113,6 +137,16 @@ HD void sincos2pi(float u, float* s, float* c)
     *s = ::sinf(6.2831853071795865f * u);
     *c = ::cosf(6.2831853071795865f * u);
 #endif
+}
+// 1/r = 1/sqrt(q) by one v_rsq_f32 and r = q / r, for a squared distance q > 0
+HD void dist_inv(float q, float& r, float& i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    i = __builtin_amdgcn_rsqf(q);
+#else
+    i = 1.0f / ::sqrtf(q);
+#endif
+    r = q * i;
 }
 
 }  // namespace m
@@ -358,12 +392,9 @@ HD void geometry(const R y[6], Geo<R>& g)
     g.D[0] = y[0] - y[3];
     g.D[1] = y[1] - y[4];
     g.D[2] = y[2] - y[5];
-    g.r1 = m::sqrt_(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    g.r2 = m::sqrt_(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
-    g.r12 = m::sqrt_(g.D[0] * g.D[0] + g.D[1] * g.D[1] + g.D[2] * g.D[2]);
-    g.i1 = m::rcp_(g.r1);
-    g.i2 = m::rcp_(g.r2);
-    g.i12 = m::rcp_(g.r12);
+    m::dist_inv(y[0] * y[0] + y[1] * y[1] + y[2] * y[2], g.r1, g.i1);
+    m::dist_inv(y[3] * y[3] + y[4] * y[4] + y[5] * y[5], g.r2, g.i2);
+    m::dist_inv(g.D[0] * g.D[0] + g.D[1] * g.D[1] + g.D[2] * g.D[2], g.r12, g.i12);
     g.p1 = y[0] * g.D[0] + y[1] * g.D[1] + y[2] * g.D[2];
     g.p2 = y[3] * g.D[0] + y[4] * g.D[1] + y[5] * g.D[2];
 }

@@ -8,6 +8,7 @@
 //               Taylor series of sin t to t^17 and cos t to t^18, quadrant k mod 4.
 //   exp(x)      x <= 0: x = k ln 2 + r, |r| <= ln2/2 (two-part ln 2), Taylor series
 //               of e^r to r^13, then 2^k by exponent scaling.
+//   expm1(x)    x <= 0: the same reduction, e^r - 1 by its series, 2^k (e^r - 1) + 2^k - 1.
 //   sqrt(x)     x >= 0: y ~ 1/sqrt(x) from the hardware seed, two Newton steps on
 //               g = x y, h = y/2 (Goldschmidt's coupled iteration), x = 0 -> 0.
 //   1/x         hardware reciprocal seed and two Newton steps, x = 0 -> inf.
@@ -207,6 +208,32 @@ HD double exp(double x)
     p = ::fma(p, r, 1.0);
     p = ::fma(p, r, 1.0);
     return k < -1100.0 ? 0.0 : ::ldexp(p, (int)k);
+}
+
+// e^x - 1 for x <= 0: x = k ln 2 + r as in exp, e^r - 1 by its Taylor series to r^13
+// (no cancellation: the series starts at r), then e^x - 1 = 2^k (e^r - 1) + (2^k - 1),
+// whose second term is exact; k = 0 returns the series itself
+HD double expm1_neg(double x)
+{
+    const double k = ::rint(x * 1.44269504088896340736);
+    const double ln2_hi = 6.93147180369123816490e-01;
+    const double ln2_lo = 1.90821492927058770002e-10;
+    const double r = ::fma(-k, ln2_lo, ::fma(-k, ln2_hi, x));  // |r| <= ln2 / 2
+    double q = 1.0 / 6227020800.0;  // 1/13!
+    q = ::fma(q, r, 1.0 / 479001600.0);
+    q = ::fma(q, r, 1.0 / 39916800.0);
+    q = ::fma(q, r, 1.0 / 3628800.0);
+    q = ::fma(q, r, 1.0 / 362880.0);
+    q = ::fma(q, r, 1.0 / 40320.0);
+    q = ::fma(q, r, 1.0 / 5040.0);
+    q = ::fma(q, r, 1.0 / 720.0);
+    q = ::fma(q, r, 1.0 / 120.0);
+    q = ::fma(q, r, 1.0 / 24.0);
+    q = ::fma(q, r, 1.0 / 6.0);
+    q = ::fma(q, r, 0.5);
+    const double em = ::fma(r * r, q, r);
+    const double p2 = k < -1100.0 ? 0.0 : ::ldexp(1.0, (int)k);  // 2^k
+    return ::fma(p2, em, p2 - 1.0);
 }
 
 }  // namespace f64

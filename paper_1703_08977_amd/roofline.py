@@ -4,24 +4,24 @@ The step is per-walker scalar arithmetic (transcendental, integer and
 floating point; no contraction, no HBM traffic between sampling times), so
 its roofline is the vector-ALU issue rate.
 
-Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s
-on the main VALU pipe, one operation per lane per clock (a wave64
-instruction occupies a 16-lane SIMD for 4 clocks).  This is the published
-78.6 TFLOP/s binary32 (and binary64) FMA rate divided by 2 flops; the 157.3
-TFLOP/s binary32 figure needs packed (v_pk_*) instructions, which this library
-does not use.
+Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s,
+one VALU instruction slot per lane per clock (a wave64 instruction occupies a
+16-lane SIMD for 4 clocks).  This is the published 78.6 TFLOP/s binary32 (and
+binary64) FMA rate divided by 2 flops; the 157.3 TFLOP/s binary32 figure needs
+packed (v_pk_*) instructions, which this library does not use.
 
-Work: every elementary operation of the step's formulas counts one slot of
-the main pipe -- add, mul, fma, compare, select, convert, 32-bit integer op,
-32x32->64 multiply, three-input xor.  The binary32 hardware transcendentals
-(v_sqrt, v_rcp, v_exp, v_log, v_sin, v_cos) are counted apart: on gfx950 they
-issue beside the main pipe (the counters of the mixed P_z step show 0.272
-wave-instructions per SIMD-cycle against 0.25 for the main pipe alone, which
-is its instruction count with the transcendentals left out).  Binary64
-library functions count their polynomial and range-reduction operations on
-the main pipe: sqrt 8, division 10, exp 20, expm1 25, -2 log 26, sincospi 35.
-Counts follow the formulas term by term (they are not read back from the
-compiled code).
+Work: every elementary operation of the step's formulas counts one slot --
+add, mul, fma, compare, select, convert, 32-bit integer op, 32x32->64
+multiply, three-input xor, and each binary32 hardware transcendental (v_sqrt,
+v_rsq, v_rcp, v_exp, v_log, v_sin, v_cos).  The transcendentals take VALU
+issue slots like the rest: the hardware counters count them among the VALU
+instructions, and over the mixed P_z step those instructions, transcendentals
+included, issue at 0.2485 wave-instructions per SIMD-cycle -- 99 % of one
+slot per cycle (0.25: a wave64 instruction holds a 16-lane SIMD for 4
+clocks).  They are also reported apart.  Binary64 library functions count their
+polynomial and range-reduction operations: sqrt 8, division 10, exp 20,
+expm1 24, -2 log 26, sincospi 35.  Counts follow the formulas term by term
+(they are not read back from the compiled code).
 """
 from __future__ import annotations
 
@@ -36,9 +36,14 @@ NODE_TRIALS = ("triplet", "triplet_r0", "pz", "pz_sum")
 # runs on the scalar unit.
 PHILOX_BLOCK = 10 * (2 + 2) - 3 - 1
 
-# (main-pipe operations, transcendental instructions) per function
-F32 = {"sqrt": (0, 1), "rcp": (0, 1), "exp": (1, 1), "expm1": (9, 1), "log": (1, 1), "sincos": (0, 2)}
-F64 = {"sqrt": (8, 0), "rcp": (10, 0), "exp": (20, 0), "expm1": (25, 0), "log": (26, 0), "sincos": (35, 0)}
+# (elementary operations, hardware transcendental instructions) per function
+# "dist": r and 1/r from a squared distance q -- binary32 one reciprocal square root and the
+# product q (1/r); binary64 a square root and a reciprocal.  "expm1" (arguments <= 0):
+# binary32 the series to x^7 beside e^x - 1 and a select, binary64 the reduced series.
+F32 = {"sqrt": (0, 1), "rcp": (0, 1), "dist": (1, 1), "exp": (1, 1), "expm1": (11, 1), "log": (1, 1),
+       "sincos": (0, 2)}
+F64 = {"sqrt": (8, 0), "rcp": (10, 0), "dist": (18, 0), "exp": (20, 0), "expm1": (24, 0), "log": (26, 0),
+       "sincos": (35, 0)}
 
 
 class _Count:
@@ -75,11 +80,10 @@ def _noise(c: _Count, f, noise: str, contract: int):
 
 
 def _trial(c: _Count, f, trial: str):
-    # geometry: D = R1 - R2 (3), three squared norms (3 x 3), sqrt and reciprocal of each,
-    # the projections R1.D and R2.D (2 x 3)
+    # geometry: D = R1 - R2 (3), three squared norms (3 x 3), the distance and its reciprocal
+    # from each, the projections R1.D and R2.D (2 x 3)
     c.ops(3 + 3 * 3 + 2 * 3)
-    c.fn(f, "sqrt", 3)
-    c.fn(f, "rcp", 3)
+    c.fn(f, "dist", 3)
     drift = 6 * 2  # b1 = a1 R1 + w D, b2 = a2 R2 - w D: a multiply and a fused add per coordinate
     if trial == "expo":
         # a_i = -A / r_i (2), b = a_i R_i (6), E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + ee/r12 (3)
@@ -143,12 +147,13 @@ def count(cfg: dict) -> _Count:
 
 
 def slots_per_walker_step(cfg: dict) -> float:
-    """Main-VALU-pipe operations of one walker step."""
-    return float(count(cfg).main)
+    """VALU issue slots of one walker step: elementary operations and hardware transcendentals."""
+    c = count(cfg)
+    return float(c.main + c.trans)
 
 
 def transcendentals_per_walker_step(cfg: dict) -> float:
-    """binary32 hardware transcendental instructions of one walker step (issued beside the main pipe)."""
+    """binary32 hardware transcendental instructions of one walker step (included in the slots)."""
     return float(count(cfg).trans)
 
 

@@ -271,7 +271,8 @@ def test_binary64_step_functions_against_the_c_library():
     err = dict(zip(out[0].split()[0::2], map(float, out[0].split()[1::2])))
     assert err["log"] <= 2.5 and err["exp"] <= 1.5 and err["sqrt"] <= 1.0 and err["rcp"] <= 1.0, err
     assert err["sin"] <= 2.0 and err["cos"] <= 2.0, err   # absolute, in units of 2^-53
-    assert out[1].split()[1:] == ["-inf", "0", "inf", "0"]
+    assert err["expm1"] <= 2.0 and err["same"] == 1.0, err
+    assert out[1].split()[1:] == ["-inf", "0", "inf", "0", "0", "-1"]
 
 
 def test_bench_reports_committed_traffic_only_for_the_profiled_configuration():
