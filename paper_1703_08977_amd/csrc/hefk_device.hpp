@@ -29,9 +29,10 @@ struct has_node {
 
 // ---------------------------------------------------------------------------
 // Elementary functions.  binary64: the lean functions of hefk_f64math.hpp
-// (a few ulp over the step's arguments) and the library expm1.  binary32: the
-// hardware approximations (v_sqrt_f32, v_rcp_f32, v_exp_f32, v_log_f32 and
-// v_sin_f32 / v_cos_f32, which take their argument in revolutions).
+// (a few ulp over the step's arguments).  binary32: the hardware approximations
+// (v_sqrt_f32, v_rsq_f32, v_rcp_f32, v_exp_f32, v_log_f32 and v_sin_f32 /
+// v_cos_f32, which take their argument in revolutions), and a short series for
+// e^x - 1 near zero.
 // ---------------------------------------------------------------------------
 namespace m {
 
@@ -46,7 +47,6 @@ HD double sqrt_(double x) { return f64::sqrt_pos(x); }
 HD double rcp_(double x) { return f64::rcp_nz(x); }
 HD double exp_(double x) { return f64::exp(x); }
 HD double expm1_(double x) { return f64::expm1_neg(x); }  // x <= 0
-HD double log_(double x) { return f64::log(x); }
 HD double neg2log_(double x) { return f64::neg2log(x); }
 // the logarithm whose base the Box-Muller radius scale assumes: natural in binary64
 HD double logb_(double x) { return f64::log_normal(x); }
@@ -101,14 +101,6 @@ HD float expm1_(float x)
     const float e = ::exp2f(x * 1.4426950408889634f);
 #endif
     return x > -0.35f ? series : e - 1.0f;
-}
-HD float log_(float x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
-#else
-    return ::logf(x);
-#endif
 }
 // -2 ln x = (-2 ln 2) log2 x: one v_log_f32 and one multiply
 HD float neg2log_(float x)
@@ -304,8 +296,8 @@ HD StepScale<double> step_scale(double dt, double drift_limit, double)
 
 // The increment sqrt(dt) xi of one step, as sqrt(dt) xi_k = r[k / 2] u[k]: for the
 // Gaussian noise a Box-Muller radius (sqrt(dt) included) and cos / sin of the angle,
-// for the +-1 walk sqrt(dt) and the signs.  Kept factored, the position update is one
-// fused multiply-add per coordinate.
+// for the +-1 walk sqrt(dt) and the signs.  Kept factored, the increment enters the
+// position update as one fused multiply-add per coordinate.
 template <typename R>
 struct Increment {
     R r[3];
@@ -579,7 +571,7 @@ HD double trial_lnpsi(const TrialParams<double>& p, const double y[6])
     const double r2 = f64::sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
     const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
     const double r12 = f64::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    const double U = (TRIAL == TRIAL_EXPO || p.c == 0.0) ? 0.0 : p.c * r12 * f64::rcp(1.0 + p.beta * r12);
+    const double U = (TRIAL == TRIAL_EXPO || p.c == 0.0) ? 0.0 : p.c * r12 * f64::rcp_nz(1.0 + p.beta * r12);
     if (TRIAL == TRIAL_EXPO || TRIAL == TRIAL_PADE) return -p.A * (r1 + r2) + U;
     // ln max(f, g) + ln|Phi / max(f, g)|
     const double d = (p.A - p.a) * (r1 - r2);
@@ -624,7 +616,7 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
         }
         const double u = unit32(w.w[3], 0.0);
         const double lpt = trial_lnpsi<TRIAL>(tp, yt);
-        if (f64::log(u) < 2.0 * (lpt - lp)) {
+        if (f64::log_normal(u) < 2.0 * (lpt - lp)) {  // u >= 2^-33
 #pragma unroll
             for (int k = 0; k < 6; ++k) y[k] = yt[k];
             lp = lpt;
@@ -675,16 +667,6 @@ inline StepConst make_step_const(double dt, double e_ref, bool quad_right, doubl
     sc.two_over_dt = 2.0 / dt;
     sc.lnw_absorbed = -INFINITY;
     return sc;
-}
-
-// ln w = -inf marks an absorbed walker (one v_cmp_class on the device)
-HD bool absorbed(double lnw)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_class(lnw, 4);  // class bit 2: negative infinity
-#else
-    return lnw == -INFINITY;
-#endif
 }
 
 // Drift / integrand limiting near singular points: f = 2 / (1 + sqrt(1 + 2 a dt |b|^2)),
