@@ -36,11 +36,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16384)
     ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle", "grad"],
                     help="copy: a plain 1 GiB device copy, three times (the reference reading of the HBM "
                          "byte counters FETCH_SIZE / WRITE_SIZE); oracle: time the CPU oracle alone on the "
                          "4096-walker ground state in full and on walkers 0..65535 of the Pade ground state "
-                         "at dt = 0.002")
+                         "at dt = 0.002; grad: the pathwise gradient of E(T = 2) for the Pade-Jastrow trial, "
+                         "2^18 walkers x 1000 steps (forward with checkpoints, then he_fk_grad), with the "
+                         "oracle's gradient timed beside it")
     return ap.parse_args()
 
 
@@ -176,6 +178,77 @@ def oracle_timing(threads=0):
     print(json.dumps(out), flush=True)
 
 
+def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu):
+    """Forward propagation with checkpoints, then the reverse sweep (he_fk_grad) of
+    dE(T)/d(alpha, beta), E(T) = e_ref - (L(T) - L(T - ds)) / ds, score term included."""
+    import numpy as np
+    import torch
+    from paper_1703_08977_amd import Ensemble, _lib, api
+    from paper_1703_08977_amd import workloads as W
+    from paper_1703_08977_amd.roofline import (GRAD_TAPE_BYTES_PER_WALKER_STEP, PEAK_SLOTS_PER_S,
+                                               grad_slots_per_walker_step)
+    cfg = W.get("he_1s_pade_grad_256k")
+    n, K, se, ce = cfg["n_walkers"], cfg["n_steps"], cfg["sample_every"], cfg["ckpt_every"]
+    ns = K // se + 1
+    dts = cfg["dt"] * se
+    ens = Ensemble(cfg)
+    samples = torch.empty((ns, 8), dtype=torch.float64, device="cuda")
+    ckpt = torch.empty((K // ce + 1, 7, n), dtype=torch.float64, device="cuda")
+    ens.workspace(K, se)
+    nb = api.he_fk_grad_scratch_bytes(ens.p, K, se, ce)
+    scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dtheta = torch.empty(2, dtype=torch.float64, device="cuda")
+    g = np.zeros(ns)
+    g[-1], g[-2] = -1.0 / dts, 1.0 / dts
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, bwd, grads = [], [], []
+    for i in range(n_warmup + n_timed):
+        ens.p.seed = i
+        ens.init()
+        ev[0].record()
+        ens.propagate(0, K, se, samples=samples, ckpt=ckpt, ckpt_every=ce)
+        ev[1].record()
+        api.he_fk_grad(ens.p, ckpt.data_ptr(), samples.data_ptr(), g, K, se, ce, _lib.GRAD_SCORE,
+                       scratch.data_ptr(), nb, dtheta.data_ptr())
+        ev[2].record()
+        torch.cuda.synchronize()
+        if i >= n_warmup:
+            fwd.append(ev[0].elapsed_time(ev[1]) / 1e3)
+            bwd.append(ev[1].elapsed_time(ev[2]) / 1e3)
+            grads.append(dtheta.cpu().tolist())
+    tf, tb = sum(fwd) / len(fwd), sum(bwd) / len(bwd)
+    slots = grad_slots_per_walker_step(cfg)
+    ach = slots * n * K / tb / 1e12
+    gbs = GRAD_TAPE_BYTES_PER_WALKER_STEP * n * K / tb / 1e9
+    out = {"mode": "grad", "workload": cfg["name"], "n_walkers": n, "n_steps": K, "ckpt_every": ce,
+           "precision": "fp64", "objective": "E(T = 2) by finite differences of L over the last sample "
+                                            "interval, start-law score term included",
+           "forward_ms": tf * 1e3, "grad_ms": tb * 1e3,
+           "grad_walker_steps_per_s": n * K / tb, "forward_and_grad_walker_steps_per_s": n * K / (tf + tb),
+           "dE_dtheta": grads,
+           "roofline": {"bound": "alu" if slots / PEAK_SLOTS_PER_S >= GRAD_TAPE_BYTES_PER_WALKER_STEP / 8e12
+                        else "hbm",
+                        "kernel": "he_fk_grad (recompute + reverse sweep)", "slots_per_walker_step": slots,
+                        "achieved": ach, "peak": PEAK_SLOTS_PER_S / 1e12, "unit": "Tslot/s",
+                        "frac": ach / (PEAK_SLOTS_PER_S / 1e12),
+                        "tape_bytes_per_walker_step": GRAD_TAPE_BYTES_PER_WALKER_STEP, "tape_GB_per_s": gbs,
+                        "tape_frac_of_8TB_s": gbs / 8000.0}}
+    if not no_cpu:
+        import oracle
+        ids = np.arange(cpu_walkers)
+        t0 = time.perf_counter()
+        y0, _ = oracle.init(cfg, ids)
+        t1 = time.perf_counter()
+        oracle.grad_objective(cfg, ids, y0, K, se, g, score=True)
+        t2 = time.perf_counter()
+        out["cpu_baseline"] = {"value": cpu_walkers * K / (t2 - t1), "unit": "walker-steps/s (gradient)",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "walker ids 0..%d, all %d steps: forward pass and the complex-step "
+                                         "derivative in each of the two directions (start ensemble %.2f s "
+                                         "apart); host CPU: %s" % (cpu_walkers - 1, K, t1 - t0, cpu_model())}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -194,6 +267,9 @@ def main():
         return
     if args.mode == "oracle":
         oracle_timing(args.oracle_threads)
+        return
+    if args.mode == "grad":
+        grad_bench(args.steps, args.warmup, args.cpu_walkers, args.no_cpu_baseline)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "

@@ -29,10 +29,10 @@ HD void vjp_trial(const TrialParams<double>& p, const double y[6], const double 
     const double R1[3] = {y[0], y[1], y[2]};
     const double R2[3] = {y[3], y[4], y[5]};
     const double D[3] = {y[0] - y[3], y[1] - y[4], y[2] - y[5]};
-    const double r1 = ::sqrt(R1[0] * R1[0] + R1[1] * R1[1] + R1[2] * R1[2]);
-    const double r2 = ::sqrt(R2[0] * R2[0] + R2[1] * R2[1] + R2[2] * R2[2]);
-    const double r12 = ::sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    const double i1 = 1.0 / r1, i2 = 1.0 / r2, i12 = 1.0 / r12;
+    double r1, r2, r12, i1, i2, i12;
+    m::dist_inv(R1[0] * R1[0] + R1[1] * R1[1] + R1[2] * R1[2], r1, i1);
+    m::dist_inv(R2[0] * R2[0] + R2[1] * R2[1] + R2[2] * R2[2], r2, i2);
+    m::dist_inv(D[0] * D[0] + D[1] * D[1] + D[2] * D[2], r12, i12);
     double h1[3], h2[3], h12[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -42,7 +42,7 @@ HD void vjp_trial(const TrialParams<double>& p, const double y[6], const double 
     }
     double up = 0.0, is = 0.0;
     if (TRIAL == TRIAL_PADE) {
-        is = 1.0 / (1.0 + p.beta * r12);
+        is = m::rcp_(1.0 + p.beta * r12);
         up = p.c * is * is;
     }
     double w = 0.0, vh = 0.0, dvh12 = 0.0;

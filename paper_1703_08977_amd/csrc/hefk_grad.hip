@@ -22,6 +22,11 @@ int check_params(const he_fk_params* p);  // hefk_kernels.hip
 namespace {
 
 constexpr int kGradBlock = 256;
+// Minimum resident waves per SIMD the gradient kernel is compiled for (register budget 512 / waves):
+// 3 keeps it free of spills (4 spills 164 B per lane and is no faster)
+#ifndef HEFK_GRAD_WAVES
+#define HEFK_GRAD_WAVES 3
+#endif
 
 struct GArgs {
     TrialParams<double> tp;
@@ -80,7 +85,7 @@ struct SampleView {
 };
 
 template <int TRIAL, int NOISE>
-__global__ __launch_bounds__(kGradBlock) void grad_kernel(const GArgs a)
+__global__ __launch_bounds__(kGradBlock, HEFK_GRAD_WAVES) void grad_kernel(const GArgs a)
 {
     __shared__ double red[8];
     const int64_t i = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;

@@ -164,3 +164,44 @@ def fp32_flops_per_walker_step(cfg: dict) -> float:
     base = {"expo": 50, "pade": 85, "triplet": 125, "triplet_r0": 130, "pz": 140, "pz_sum": 130}[cfg["trial"]]
     noise = 0 if cfg.get("noise", "gauss") == "pm1" else 3 * 6 + 6
     return float(12 * 2 + base + noise)
+
+
+def _vjp(c: _Count, f, trial: str):
+    """One reverse step of the pathwise gradient (binary64): the vector-Jacobian product of
+    F = V . b(Y) + A e(Y) through the trial evaluation, and the sweep's own updates."""
+    # geometry again: D (3), squared norms (9), distance and reciprocal of each, unit vectors (9)
+    c.ops(3 + 9 + 9)
+    c.fn(f, "dist", 3)
+    if trial == "pade":
+        c.ops(1 + 2)  # s = 1 + beta r12, u' = c / s^2
+        c.fn(f, "rcp")
+    # w = (h1 - h2).h12 (6), V.h (6), (V1 - V2).h12 (6)
+    c.ops(6 + 6 + 6)
+    # adjoints of the unit vectors: A alpha u' (2), bh1 and bh2 (2 x 3 x 2), bh12 (3 x 4)
+    c.ops(2 + 12 + 12)
+    # adjoints of 1/r1 = 1/r2 and 1/r12, d/d alpha (9)
+    c.ops(2 + 2 + 5)
+    if trial == "pade":
+        # d/du', d/d(1/s), d/d beta, d/ds, its share of d/dr12 (17)
+        c.ops(5 + 5 + 3 + 2 + 2)
+    # back through r = |R|, h = R/r: three projections (9), their sums (3), d/dr (6), grad Y (3 x 7)
+    c.ops(9 + 3 + 6 + 21)
+    # sweep: V = dt lambda (6), lambda += grad (6), theta-bar (2), the step's weight A (2), P += H (1)
+    c.ops(6 + 6 + 2 + 2 + 1)
+
+
+# Tape traffic of the reverse sweep per walker-step: the recomputed state (6 coordinates and
+# ln w, binary64) written once and read back once.
+GRAD_TAPE_BYTES_PER_WALKER_STEP = 2 * 7 * 8
+
+
+def grad_slots_per_walker_step(cfg: dict) -> float:
+    """VALU issue slots of the gradient kernel per walker-step: the recomputed forward step
+    (plus the segment's start evaluation, once per checkpoint interval) and the reverse step."""
+    fwd = count(dict(cfg, precision="fp64"))
+    c = _Count()
+    _trial(c, F64, cfg["trial"])
+    v = _Count()
+    _vjp(v, F64, cfg["trial"])
+    ce = max(1, int(cfg.get("ckpt_every", 50)))
+    return float(fwd.main + fwd.trans + (c.main + c.trans) / ce + v.main + v.trans)
