@@ -50,8 +50,10 @@ def rel_err(a, b):
 
 
 def log_mean_weight(samples):
+    """L = m + ln S0 - ln N per sample row (-inf where every walker is absorbed)."""
     s = np.asarray(samples, dtype=np.float64)
-    return s[:, 0] + np.log(s[:, 1]) - np.log(s[:, 6])
+    with np.errstate(divide="ignore"):
+        return s[:, 0] + np.log(s[:, 1]) - np.log(s[:, 6])
 
 
 _HARNESS = None

@@ -40,6 +40,8 @@ def _compare(g, r, tol=TOL, node=False):
     ex = rel_err(g["x"][alive], r["x"][alive]).max(axis=1) if alive.any() else np.zeros(0)
     el = rel_err(g["lnw"][alive], r["lnw"][alive])
     worst = np.maximum(ex, el)
+    if worst.size == 0:  # every walker absorbed: nothing left to compare
+        return ex, el
     if not node:
         assert worst.max(initial=0.0) < tol, (ex.max(initial=0), el.max(initial=0))
     else:
