@@ -172,6 +172,34 @@ def test_mixed_precision_variants_close_to_binary64(over):
     assert np.abs(Lg - Lr).max() < 2e-2
 
 
+MIXED_TRIALS = [
+    ("he_1s_expo_4k", dict()),
+    ("he_1s_pade_1m", dict(dt=0.002)),
+    ("he_2tripS_4m", dict(dt=0.002)),
+    ("he_2tripS_fn5_1m", dict()),
+    ("he_2P_fn7_1m", dict()),
+    ("he_2P_pz_16m", dict(dt=0.002, sym=-1, theta=[2.0, 0.3, 0.25, 0.5])),
+]
+
+
+@pytest.mark.parametrize("name,over", MIXED_TRIALS, ids=lambda v: str(v))
+def test_mixed_precision_trials_close_to_binary64(name, over):
+    # every trial family in the binary32 step against the binary64 oracle on the same streams:
+    # the same start ensemble (rounded), the same absorption decisions for nearly every walker,
+    # weights within the binary32 rounding of the paths
+    cfg = W.get(name, precision="mixed", **over)
+    n = 4096
+    g = gpu_run(cfg, n_walkers=n, n_steps=400, sample_every=20)
+    r = oracle.run(dict(cfg, precision="fp64"), np.arange(n), 400, 20)
+    assert np.abs(g["x0"] - r["x0"]).max() <= 2.0**-23 * max(1.0, np.abs(r["x0"]).max())
+    assert (np.isfinite(g["lnw"]) == np.isfinite(r["lnw"])).mean() > 0.97
+    both = np.isfinite(g["lnw"]) & np.isfinite(r["lnw"])
+    assert both.mean() > 0.5
+    assert np.median(np.abs(g["lnw"][both] - r["lnw"][both])) < 1e-4
+    Lg, Lr = log_mean_weight(g["samples"]), log_mean_weight(r["samples"])
+    assert np.abs(Lg - Lr).max() < 2e-2
+
+
 def test_exact_system_weights_on_gpu():
     cfg = W.get("exact_noee")
     g = gpu_run(cfg, n_walkers=10000, n_steps=400, sample_every=20)
