@@ -37,6 +37,10 @@ struct has_node {
 namespace m {
 
 HD double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// -|a|: binary32 as a negated absolute value (operand modifiers of the consumer),
+// binary64 as a select, which schedules better in the binary64 step
+HD double negabs_(double a) { return a <= 0.0 ? a : -a; }
+HD float negabs_(float a) { return -__builtin_fabsf(a); }
 HD double copysign_(double a, double b) { return __builtin_copysign(a, b); }
 HD float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
 HD float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -457,12 +461,13 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
         const bool lo = d <= (R)0;
-        R g1, g2, l1, l2, D;
+        R g1, g2, lsum, D;  // lsum = Lap_1 Phi / Phi + Lap_2 Phi / Phi
         if (TRIAL == TRIAL_TRIPLET) {
             // Phi / max(f, g) = t1 - t2 = D:
             //   g1 = (-A t1 + a t2) / D, g2 = (-a t1 + A t2) / D,
             //   Lap_1 Phi / Phi = [t1 (A^2 - 2A/r1) - t2 (a^2 - 2a/r1)] / D (roles exchanged for Lap_2)
-            const R em = m::expm1_(lo ? d : -d);  // e^{-|d|} - 1, accurate near the node
+            //   (kept as two ratios: the form with the brackets combined measured slower)
+            const R em = m::expm1_(m::negabs_(d));  // e^{-|d|} - 1, accurate near the node
             const R e = (R)1 + em;
             const R t1 = lo ? (R)1 : e;
             const R t2 = lo ? e : (R)1;
@@ -470,12 +475,13 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
             const R iD = m::rcp_(D);
             g1 = (-p.A * t1 + p.a * t2) * iD;
             g2 = (-p.a * t1 + p.A * t2) * iD;
-            l1 = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) - t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
-            l2 = (t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
+            lsum = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) - t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD +
+                   (t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
         } else {
             // Phi / max(f, g) = (r0 - r1) t1 - (r0 - r2) t2 = D; with u(r) = (r0 - r) e^{-A r}:
-            //   u'/e^{-A r} = -(1 + A (r0 - r)),  Lap u / e^{-A r} = A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r
-            const R e = m::exp_(lo ? d : -d);
+            //   u'/e^{-A r} = -(1 + A (r0 - r)),  Lap u / e^{-A r} = A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r;
+            //   the two Laplacian ratios summed by their t1 and t2 terms
+            const R e = m::exp_(m::negabs_(d));  // e^{-|d|}
             const R t1 = lo ? (R)1 : e;
             const R t2 = lo ? e : (R)1;
             const R q1 = p.r0 - g.r1, q2 = p.r0 - g.r2;
@@ -484,14 +490,14 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
             const R u1 = (R)1 + p.A * q1, u2 = (R)1 + p.A * q2;
             g1 = (-u1 * t1 + p.a * q2 * t2) * iD;
             g2 = (-p.a * q1 * t1 + u2 * t2) * iD;
-            l1 = (t1 * (p.A * ((R)2 + p.A * q1) - (R)2 * u1 * g.i1) - q2 * t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD;
-            l2 = (q1 * t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * ((R)2 + p.A * q2) - (R)2 * u2 * g.i2)) * iD;
+            lsum = (t1 * (p.A * ((R)2 + p.A * q1) - (R)2 * u1 * g.i1 + q1 * (p.a * p.a - (R)2 * p.a * g.i2)) -
+                    t2 * (p.A * ((R)2 + p.A * q2) - (R)2 * u2 * g.i2 + q2 * (p.a * p.a - (R)2 * p.a * g.i1))) * iD;
         }
         // grad_i Phi / Phi = g_i h_i
         drift_from(y, g, g1 * g.i1, g2 * g.i2, j.up * g.i12, b);
         if (gphi2) *gphi2 = g1 * g1 + g2 * g2;
         const R cross = (g1 * g.p1 * g.i1 - g2 * g.p2 * g.i2) * g.i12;  // g1 h1.h12 - g2 h2.h12
-        el = (R)-0.5 * (l1 + l2) - j.up * cross - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        el = (R)-0.5 * lsum - j.up * cross - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         node = D;
     } else if (TRIAL == TRIAL_PZ_SUM) {
         // Phi = (z1 + z2)(f + g) (trial function 7): with Zs = z1 + z2 and S = f + g,
@@ -500,7 +506,7 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
         const bool lo = d <= (R)0;
-        const R e = m::exp_(lo ? d : -d);
+        const R e = m::exp_(m::negabs_(d));  // e^{-|d|}
         const R t1 = lo ? (R)1 : e;
         const R t2 = lo ? e : (R)1;
         const R iS = m::rcp_(t1 + t2);
@@ -515,19 +521,19 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         b[5] += iZ;
         if (gphi2)
             *gphi2 = g1 * g1 + g2 * g2 + (R)2 * iZ * (a1 * z1 + a2 * z2 + iZ);
-        const R l1 = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) + t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iS +
-                     (R)2 * a1 * z1 * iZ;
-        const R l2 = (t1 * (p.a * p.a - (R)2 * p.a * g.i2) + t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iS +
-                     (R)2 * a2 * z2 * iZ;
+        // Lap_1 Phi / Phi + Lap_2 Phi / Phi, summed by the t1 and t2 terms
+        const R q = p.A * p.A + p.a * p.a;
+        const R lsum = (t1 * (q - (R)2 * p.A * g.i1 - (R)2 * p.a * g.i2) + t2 * (q - (R)2 * p.a * g.i1 - (R)2 * p.A * g.i2)) * iS +
+                       (R)2 * iZ * (a1 * z1 + a2 * z2);
         // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12: the zhat / Zs terms cancel
         const R cr = (a1 * g.p1 - a2 * g.p2) * g.i12;
-        el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        el = (R)-0.5 * lsum - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         node = Zs;
     } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
         const bool lo = d <= (R)0;
-        const R e = m::exp_(lo ? d : -d);
+        const R e = m::exp_(m::negabs_(d));  // e^{-|d|}
         const R t1 = lo ? (R)1 : e;
         const R t2 = (lo ? e : (R)1) * p.sym;
         const R z1 = y[2], z2 = y[5];
@@ -544,11 +550,14 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         if (gphi2)
             *gphi2 = a1 * a1 * g.r1 * g.r1 + (R)2 * a1 * s1 * z1 + s1 * s1 + a2 * a2 * g.r2 * g.r2 +
                      (R)2 * a2 * s2 * z2 + s2 * s2;
-        const R l1 = (z2 * t1 * (p.A * p.A - (R)2 * p.A * g.i1) + t2 * z1 * (p.a * p.a - (R)4 * p.a * g.i1)) * iP;
-        const R l2 = (z2 * t1 * (p.a * p.a - (R)4 * p.a * g.i2) + t2 * z1 * (p.A * p.A - (R)2 * p.A * g.i2)) * iP;
+        // Lap_1 Phi / Phi + Lap_2 Phi / Phi, both electrons' terms of each product combined:
+        // [z2 t1 (A^2 + a^2 - 2A/r1 - 4a/r2) + t2 z1 (A^2 + a^2 - 4a/r1 - 2A/r2)] / P
+        const R q = p.A * p.A + p.a * p.a;
+        const R lsum = (z2 * t1 * (q - (R)2 * p.A * g.i1 - (R)4 * p.a * g.i2) +
+                        t2 * z1 * (q - (R)4 * p.a * g.i1 - (R)2 * p.A * g.i2)) * iP;
         // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12
         const R cr = (a1 * g.p1 - a2 * g.p2 + (s1 - s2) * g.D[2]) * g.i12;
-        el = (R)-0.5 * (l1 + l2) - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        el = (R)-0.5 * lsum - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
         node = P;
     }
     return node;

@@ -16,9 +16,9 @@ multiply, three-input xor, and each binary32 hardware transcendental (v_sqrt,
 v_rsq, v_rcp, v_exp, v_log, v_sin, v_cos).  The transcendentals take VALU
 issue slots like the rest: the hardware counters count them among the VALU
 instructions, and over the mixed P_z step those instructions, transcendentals
-included, issue at 0.2485 wave-instructions per SIMD-cycle -- 99 % of one
-slot per cycle (0.25: a wave64 instruction holds a 16-lane SIMD for 4
-clocks).  They are also reported apart.  Binary64 library functions count their
+included, issue at 0.250 wave-instructions per SIMD-cycle -- one slot per
+cycle (a wave64 instruction holds a 16-lane SIMD for 4 clocks).  They are
+also reported apart.  Binary64 library functions count their
 polynomial and range-reduction operations: sqrt 8, division 10, exp 20,
 expm1 24, -2 log 26, sincospi 35.  Counts follow the formulas term by term
 (they are not read back from the compiled code).
@@ -97,31 +97,35 @@ def _trial(c: _Count, f, trial: str):
         # E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + A u' cos - u'' - u'^2 + ee term (7)
         c.ops(2 + 1 + drift + 3 + 7)
         return
-    # d = (A - a)(r1 - r2) (2), its sign (1), the argument -|d| (2), the pair (t1, t2) (2)
-    c.ops(2 + 1 + 2 + 2)
+    # d = (A - a)(r1 - r2) (2), its sign (1), the pair (t1, t2) (2); the argument -|d| is an
+    # operand modifier in binary32 and a select in binary64
+    c.ops(2 + 1 + 2 + (1 if f is F64 else 0))
     if trial == "triplet":
         c.fn(f, "expm1")
         c.fn(f, "rcp")
-        # e = 1 + em, D (2), g1, g2 (2 x 3), Laplacian ratios (2 x 6), g_i / r_i (2), w (1), drift,
-        # cross term (5), E_L (8)
-        c.ops(1 + 2 + 6 + 12 + 2 + 1 + drift + 5 + 8)
+        # e = 1 + em, D (2), g1, g2 (2 x 3), the two Laplacian ratios (2 x 5) and their sum (1),
+        # g_i / r_i (2), w (1), drift, cross term (5), E_L (7)
+        c.ops(1 + 2 + 6 + 11 + 2 + 1 + drift + 5 + 7)
         return
     c.fn(f, "exp")
     c.fn(f, "rcp")
     if trial == "triplet_r0":
-        # q_i = r0 - r_i, u_i = 1 + A q_i (4), D (2), g1, g2 (2 x 4), Laplacian ratios (2 x 8),
-        # g_i / r_i (2), w (1), drift, cross term (5), E_L (8)
-        c.ops(4 + 2 + 8 + 16 + 2 + 1 + drift + 5 + 8)
+        # q_i = r0 - r_i, u_i = 1 + A q_i (4), D (2), g1, g2 (2 x 4), the sum of the two Laplacian
+        # ratios (two brackets of five operations, t1 and t2 times them, 1/D: 13), g_i / r_i (2),
+        # w (1), drift, cross term (5), E_L (7)
+        c.ops(4 + 2 + 8 + 13 + 2 + 1 + drift + 5 + 7)
         return
     if trial == "pz_sum":
         c.fn(f, "rcp")  # 1 / (z1 + z2)
-        # t1 + t2 (1), z1 + z2 (1), g1, g2 (2 x 3), a_i (2), w (1), drift, z terms (2), node-gradient
-        # Laplacian ratios (2 x 8), cross term (3), E_L (8)
-        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 16 + 3 + 8)
+        # t1 + t2 (1), z1 + z2 (1), g1, g2 (2 x 3), a_i (2), w (1), drift, z terms (2), the sum of
+        # the two Laplacian ratios (brackets 4, t1 and t2 times them 2, 1/S 1, the node-gradient
+        # term 2 iZ (a1 z1 + a2 z2) 4: 11), cross term (3), E_L (7)
+        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 11 + 3 + 7)
         return
     # P_z: sym t2 (1), P (2), k1, k2 (2 x 4), a1, a2 (2 x 2), s1, s2 (2), w (1), drift, z terms (2),
-    # Laplacian ratios (2 x 7), cross term (5), E_L (8)
-    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 14 + 5 + 8)
+    # the sum of the two Laplacian ratios (two brackets of two fused multiply-adds, the products
+    # z2 t1 and t2 z1 and their combination with the brackets, 1/P: 9), cross term (5), E_L (7)
+    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 9 + 5 + 7)
 
 
 def count(cfg: dict) -> _Count:
