@@ -395,13 +395,14 @@ HD void geometry(const R y[6], Geo<R>& g)
     g.p2 = y[3] * g.D[0] + y[4] * g.D[1] + y[5] * g.D[2];
 }
 
-// Jastrow pieces: u' = c / s^2, u'' = -2 c beta / s^3, and
-// (ee - 2 u') / r12 written without the cancellation at r12 -> 0 when
-// ee = 2c (the cusp value): (ee - 2c)/r12 + 2c beta (2 + beta r12) / s^2,
-// from 1 - 1/s^2 = beta r12 (2 + beta r12) / s^2.
+// Jastrow pieces: u' = c / s^2 (s = 1 + beta r12) and the radial part of the local
+// energy's Jastrow terms,
+//   rest = -u'' - u'^2 + (ee - 2u')/r12 = [2 c beta (1/s + 2 + beta r12) - c^2 / s^2] / s^2 + (ee - 2c)/r12,
+// with u'' = -2 c beta / s^3, and (ee - 2u')/r12 written without the cancellation at
+// r12 -> 0 when ee = 2c (the cusp value), from 1 - 1/s^2 = beta r12 (2 + beta r12) / s^2.
 template <typename R>
 struct Jas {
-    R up, upp, ee_term;
+    R up, rest;
 };
 
 template <typename R>
@@ -411,9 +412,9 @@ HD Jas<R> jastrow(const TrialParams<R>& p, const Geo<R>& g)
     const R is = m::rcp_((R)1 + p.beta * g.r12);
     const R is2 = is * is;
     j.up = p.c * is2;
-    j.upp = (R)-2 * p.c * p.beta * is2 * is;
     const R cusp = p.ee - (R)2 * p.c;
-    j.ee_term = (R)2 * p.c * p.beta * ((R)2 + p.beta * g.r12) * is2 + (cusp != (R)0 ? cusp * g.i12 : (R)0);
+    j.rest = ((R)2 * p.c * p.beta * (is + (R)2 + p.beta * g.r12) - p.c * p.c * is2) * is2 +
+             (cusp != (R)0 ? cusp * g.i12 : (R)0);
     return j;
 }
 
@@ -423,8 +424,9 @@ HD void drift_from(const R y[6], const Geo<R>& g, R a1, R a2, R w, R b[6])
 {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        b[k] = a1 * y[k] + w * g.D[k];
-        b[3 + k] = a2 * y[3 + k] - w * g.D[k];
+        const R wd = w * g.D[k];  // shared by both electrons
+        b[k] = m::fma_(a1, y[k], wd);
+        b[3 + k] = m::fma_(a2, y[3 + k], -wd);
     }
 }
 
@@ -456,7 +458,7 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         drift_from(y, g, -p.A * g.i1, -p.A * g.i2, j.up * g.i12, b);
         if (gphi2) *gphi2 = (R)2 * p.A * p.A;
         const R w = (g.p1 * g.i1 - g.p2 * g.i2) * g.i12;  // (h1 - h2) . h12
-        el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + p.A * j.up * w - j.upp - j.up * j.up + j.ee_term;
+        el = -p.A * p.A + (p.A - p.Z) * (g.i1 + g.i2) + p.A * j.up * w + j.rest;
     } else if (TRIAL == TRIAL_TRIPLET || TRIAL == TRIAL_TRIPLET_R0) {
         const Jas<R> j = jastrow(p, g);
         const R d = (p.A - p.a) * (g.r1 - g.r2);
@@ -465,8 +467,8 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         if (TRIAL == TRIAL_TRIPLET) {
             // Phi / max(f, g) = t1 - t2 = D:
             //   g1 = (-A t1 + a t2) / D, g2 = (-a t1 + A t2) / D,
-            //   Lap_1 Phi / Phi = [t1 (A^2 - 2A/r1) - t2 (a^2 - 2a/r1)] / D (roles exchanged for Lap_2)
-            //   (kept as two ratios: the form with the brackets combined measured slower)
+            //   Lap_1 Phi / Phi = [t1 (A^2 - 2A/r1) - t2 (a^2 - 2a/r1)] / D (roles exchanged for Lap_2),
+            //   summed: [t1 (A^2 + a^2 - 2A/r1 - 2a/r2) - t2 (A^2 + a^2 - 2a/r1 - 2A/r2)] / D
             const R em = m::expm1_(m::negabs_(d));  // e^{-|d|} - 1, accurate near the node
             const R e = (R)1 + em;
             const R t1 = lo ? (R)1 : e;
@@ -475,8 +477,8 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
             const R iD = m::rcp_(D);
             g1 = (-p.A * t1 + p.a * t2) * iD;
             g2 = (-p.a * t1 + p.A * t2) * iD;
-            lsum = (t1 * (p.A * p.A - (R)2 * p.A * g.i1) - t2 * (p.a * p.a - (R)2 * p.a * g.i1)) * iD +
-                   (t1 * (p.a * p.a - (R)2 * p.a * g.i2) - t2 * (p.A * p.A - (R)2 * p.A * g.i2)) * iD;
+            const R q = p.A * p.A + p.a * p.a;
+            lsum = (t1 * (q - (R)2 * p.A * g.i1 - (R)2 * p.a * g.i2) - t2 * (q - (R)2 * p.a * g.i1 - (R)2 * p.A * g.i2)) * iD;
         } else {
             // Phi / max(f, g) = (r0 - r1) t1 - (r0 - r2) t2 = D; with u(r) = (r0 - r) e^{-A r}:
             //   u'/e^{-A r} = -(1 + A (r0 - r)),  Lap u / e^{-A r} = A (2 + A (r0 - r)) - 2 (1 + A (r0 - r)) / r;
@@ -497,7 +499,7 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
         drift_from(y, g, g1 * g.i1, g2 * g.i2, j.up * g.i12, b);
         if (gphi2) *gphi2 = g1 * g1 + g2 * g2;
         const R cross = (g1 * g.p1 * g.i1 - g2 * g.p2 * g.i2) * g.i12;  // g1 h1.h12 - g2 h2.h12
-        el = (R)-0.5 * lsum - j.up * cross - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        el = (R)-0.5 * lsum - j.up * cross + j.rest - p.Z * (g.i1 + g.i2);
         node = D;
     } else if (TRIAL == TRIAL_PZ_SUM) {
         // Phi = (z1 + z2)(f + g) (trial function 7): with Zs = z1 + z2 and S = f + g,
@@ -527,7 +529,7 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
                        (R)2 * iZ * (a1 * z1 + a2 * z2);
         // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12: the zhat / Zs terms cancel
         const R cr = (a1 * g.p1 - a2 * g.p2) * g.i12;
-        el = (R)-0.5 * lsum - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        el = (R)-0.5 * lsum - j.up * cr + j.rest - p.Z * (g.i1 + g.i2);
         node = Zs;
     } else {  // TRIAL_PZ: Phi / max(f, g) = P = z2 t1 + sym z1 t2
         const Jas<R> j = jastrow(p, g);
@@ -557,7 +559,7 @@ HD R trial_eval(const TrialParams<R>& p, const R y[6], R b[6], R& el, R* gphi2 =
                         t2 * z1 * (q - (R)4 * p.a * g.i1 - (R)2 * p.A * g.i2)) * iP;
         // (grad_1 Phi / Phi - grad_2 Phi / Phi) . h12
         const R cr = (a1 * g.p1 - a2 * g.p2 + (s1 - s2) * g.D[2]) * g.i12;
-        el = (R)-0.5 * lsum - j.up * cr - j.upp - j.up * j.up + j.ee_term - p.Z * (g.i1 + g.i2);
+        el = (R)-0.5 * lsum - j.up * cr + j.rest - p.Z * (g.i1 + g.i2);
         node = P;
     }
     return node;

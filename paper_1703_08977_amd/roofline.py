@@ -84,18 +84,20 @@ def _trial(c: _Count, f, trial: str):
     # from each, the projections R1.D and R2.D (2 x 3)
     c.ops(3 + 3 * 3 + 2 * 3)
     c.fn(f, "dist", 3)
-    drift = 6 * 2  # b1 = a1 R1 + w D, b2 = a2 R2 - w D: a multiply and a fused add per coordinate
+    drift = 3 * 3  # b1 = a1 R1 + w D, b2 = a2 R2 - w D: w D once per component, a fused multiply-add per coordinate
     if trial == "expo":
         # a_i = -A / r_i (2), b = a_i R_i (6), E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + ee/r12 (3)
         c.ops(2 + 6 + 3)
         return
-    # Jastrow: 1 + beta r12 and its reciprocal, 1/s^2, u', u'', the cusp-free ee term (4)
-    c.ops(1 + 1 + 1 + 2 + 4)
+    # Jastrow: s = 1 + beta r12 and its reciprocal, 1/s^2, u', and the radial part of the local
+    # energy's Jastrow terms [2 c beta (1/s + 2 + beta r12) - c^2 / s^2] / s^2 (5) plus the cusp
+    # remainder (ee - 2c)/r12 (product, select, sum: 3)
+    c.ops(1 + 1 + 1 + 5 + 3)
     c.fn(f, "rcp")
     if trial == "pade":
         # a_i (2), w = u'/r12 (1), drift, cosine difference (3),
-        # E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + A u' cos - u'' - u'^2 + ee term (7)
-        c.ops(2 + 1 + drift + 3 + 7)
+        # E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + A u' cos + the Jastrow radial part (5)
+        c.ops(2 + 1 + drift + 3 + 5)
         return
     # d = (A - a)(r1 - r2) (2), its sign (1), the pair (t1, t2) (2); the argument -|d| is an
     # operand modifier in binary32 and a select in binary64
@@ -103,29 +105,30 @@ def _trial(c: _Count, f, trial: str):
     if trial == "triplet":
         c.fn(f, "expm1")
         c.fn(f, "rcp")
-        # e = 1 + em, D (2), g1, g2 (2 x 3), the two Laplacian ratios (2 x 5) and their sum (1),
-        # g_i / r_i (2), w (1), drift, cross term (5), E_L (7)
-        c.ops(1 + 2 + 6 + 11 + 2 + 1 + drift + 5 + 7)
+        # e = 1 + em, D (2), g1, g2 (2 x 3), the sum of the two Laplacian ratios (two brackets of
+        # two fused multiply-adds, t1 and t2 times them, 1/D: 7), g_i / r_i (2), w (1), drift,
+        # cross term (5), E_L (5)
+        c.ops(1 + 2 + 6 + 7 + 2 + 1 + drift + 5 + 5)
         return
     c.fn(f, "exp")
     c.fn(f, "rcp")
     if trial == "triplet_r0":
         # q_i = r0 - r_i, u_i = 1 + A q_i (4), D (2), g1, g2 (2 x 4), the sum of the two Laplacian
         # ratios (two brackets of five operations, t1 and t2 times them, 1/D: 13), g_i / r_i (2),
-        # w (1), drift, cross term (5), E_L (7)
-        c.ops(4 + 2 + 8 + 13 + 2 + 1 + drift + 5 + 7)
+        # w (1), drift, cross term (5), E_L (5)
+        c.ops(4 + 2 + 8 + 13 + 2 + 1 + drift + 5 + 5)
         return
     if trial == "pz_sum":
         c.fn(f, "rcp")  # 1 / (z1 + z2)
         # t1 + t2 (1), z1 + z2 (1), g1, g2 (2 x 3), a_i (2), w (1), drift, z terms (2), the sum of
         # the two Laplacian ratios (brackets 4, t1 and t2 times them 2, 1/S 1, the node-gradient
-        # term 2 iZ (a1 z1 + a2 z2) 4: 11), cross term (3), E_L (7)
-        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 11 + 3 + 7)
+        # term 2 iZ (a1 z1 + a2 z2) 4: 11), cross term (3), E_L (5)
+        c.ops(1 + 1 + 6 + 2 + 1 + drift + 2 + 11 + 3 + 5)
         return
     # P_z: sym t2 (1), P (2), k1, k2 (2 x 4), a1, a2 (2 x 2), s1, s2 (2), w (1), drift, z terms (2),
     # the sum of the two Laplacian ratios (two brackets of two fused multiply-adds, the products
-    # z2 t1 and t2 z1 and their combination with the brackets, 1/P: 9), cross term (5), E_L (7)
-    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 9 + 5 + 7)
+    # z2 t1 and t2 z1 and their combination with the brackets, 1/P: 9), cross term (5), E_L (5)
+    c.ops(1 + 2 + 8 + 4 + 2 + 1 + drift + 2 + 9 + 5 + 5)
 
 
 def count(cfg: dict) -> _Count:
