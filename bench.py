@@ -185,8 +185,8 @@ def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu):
     import torch
     from paper_1703_08977_amd import Ensemble, _lib, api
     from paper_1703_08977_amd import workloads as W
-    from paper_1703_08977_amd.roofline import (GRAD_TAPE_BYTES_PER_WALKER_STEP, PEAK_SLOTS_PER_S,
-                                               grad_slots_per_walker_step)
+    from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, grad_slots_per_walker_step,
+                                               grad_tape_bytes_per_walker_step)
     cfg = W.get("he_1s_pade_grad_256k")
     n, K, se, ce = cfg["n_walkers"], cfg["n_steps"], cfg["sample_every"], cfg["ckpt_every"]
     ns = K // se + 1
@@ -218,20 +218,20 @@ def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu):
             grads.append(dtheta.cpu().tolist())
     tf, tb = sum(fwd) / len(fwd), sum(bwd) / len(bwd)
     slots = grad_slots_per_walker_step(cfg)
+    tape = grad_tape_bytes_per_walker_step(cfg)
     ach = slots * n * K / tb / 1e12
-    gbs = GRAD_TAPE_BYTES_PER_WALKER_STEP * n * K / tb / 1e9
+    gbs = tape * n * K / tb / 1e9
     out = {"mode": "grad", "workload": cfg["name"], "n_walkers": n, "n_steps": K, "ckpt_every": ce,
            "precision": "fp64", "objective": "E(T = 2) by finite differences of L over the last sample "
                                             "interval, start-law score term included",
            "forward_ms": tf * 1e3, "grad_ms": tb * 1e3,
            "grad_walker_steps_per_s": n * K / tb, "forward_and_grad_walker_steps_per_s": n * K / (tf + tb),
            "dE_dtheta": grads,
-           "roofline": {"bound": "alu" if slots / PEAK_SLOTS_PER_S >= GRAD_TAPE_BYTES_PER_WALKER_STEP / 8e12
-                        else "hbm",
+           "roofline": {"bound": "alu" if slots / PEAK_SLOTS_PER_S >= tape / 8e12 else "hbm",
                         "kernel": "he_fk_grad (recompute + reverse sweep)", "slots_per_walker_step": slots,
                         "achieved": ach, "peak": PEAK_SLOTS_PER_S / 1e12, "unit": "Tslot/s",
                         "frac": ach / (PEAK_SLOTS_PER_S / 1e12),
-                        "tape_bytes_per_walker_step": GRAD_TAPE_BYTES_PER_WALKER_STEP, "tape_GB_per_s": gbs,
+                        "tape_bytes_per_walker_step": tape, "tape_GB_per_s": gbs,
                         "tape_frac_of_8TB_s": gbs / 8000.0}}
     if not no_cpu:
         import oracle

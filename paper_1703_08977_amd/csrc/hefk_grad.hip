@@ -57,20 +57,20 @@ struct DeviceTape {
         for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
         lnw = b[6 * n + i];
     }
-    __device__ void put(int slot, const double y[6], double lnw)
+    __device__ void put(int slot, const double y[6])
     {
         double* b = tape + (size_t)slot * 7 * n;
 #pragma unroll
         for (int k = 0; k < 6; ++k) b[(int64_t)k * n + i] = y[k];
-        b[6 * n + i] = lnw;
     }
-    __device__ void get(int slot, double y[6], double& lnw) const
+    __device__ void put_lnw(int slot, double lnw) { tape[(size_t)slot * 7 * n + 6 * n + i] = lnw; }
+    __device__ void get(int slot, double y[6]) const
     {
         const double* b = tape + (size_t)slot * 7 * n;
 #pragma unroll
         for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
-        lnw = b[6 * n + i];
     }
+    __device__ double get_lnw(int slot) const { return tape[(size_t)slot * 7 * n + 6 * n + i]; }
 };
 
 struct SampleView {

@@ -24,21 +24,26 @@ HD void walker_reverse(const TrialParams<double>& tp, const StepConst& sc, const
         WalkerState<double> w;
         tape.load_ckpt(seg, w.y, w.lnw);
         walker_reset<double, TRIAL>(tp, sc, ss, w);
-        tape.put(0, w.y, w.lnw);
+        // the tape holds every step's position, and ln w only where the reverse pass reads
+        // it: at the sampling steps
+        tape.put(0, w.y);
+        if (k0 % sample_every == 0) tape.put_lnw(0, w.lnw);
         NoiseGen<double, NOISE> noise;
         for (int k = 0; k < ckpt_every; ++k) {
             Increment<double> inc;
             noise.draw(st, (uint32_t)(k0 + k), ss, inc);
             walker_step<double, TRIAL>(tp, sc, ss, inc, w);
-            tape.put(k + 1, w.y, w.lnw);
+            tape.put(k + 1, w.y);
+            if ((k0 + k + 1) % sample_every == 0) tape.put_lnw(k + 1, w.lnw);
         }
         // reverse over the steps of the segment (step k0 belongs to the segment below, except k0 = 0)
         const int j_lo = (seg == 0) ? 0 : k0 + 1;
         for (int j = k0 + ckpt_every; j >= j_lo; --j) {
-            double y[6], lnw;
-            tape.get(j - k0, y, lnw);
+            double y[6];
+            tape.get(j - k0, y);
             double H = 0.0;
             if (j % sample_every == 0) {
+                const double lnw = tape.get_lnw(j - k0);
                 // dJ/d ln w_j: g_s p_is + 2 g2_s q_is, with the walker's shares
                 // p_is = w / sum w of L_s and q_is = w^2 / sum w^2 of L2_s
                 const int s = j / sample_every;

@@ -197,9 +197,10 @@ def _vjp(c: _Count, f, trial: str):
     c.ops(6 + 6 + 2 + 2 + 1)
 
 
-# Tape traffic of the reverse sweep per walker-step: the recomputed state (6 coordinates and
-# ln w, binary64) written once and read back once.
-GRAD_TAPE_BYTES_PER_WALKER_STEP = 2 * 7 * 8
+def grad_tape_bytes_per_walker_step(cfg: dict) -> float:
+    """Tape traffic of the reverse sweep per walker-step: the recomputed position (6 binary64
+    coordinates) written once and read back once, and ln w likewise at the sampling steps."""
+    return 2.0 * 6 * 8 + 2.0 * 8 / max(1, int(cfg.get("sample_every", 1)))
 
 
 def grad_slots_per_walker_step(cfg: dict) -> float:

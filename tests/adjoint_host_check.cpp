@@ -20,16 +20,16 @@ struct HostTape {
         for (int k = 0; k < 6; ++k) y[k] = ck[7 * c + k];
         lnw = ck[7 * c + 6];
     }
-    void put(int s, const double y[6], double lnw)
+    void put(int s, const double y[6])
     {
         for (int k = 0; k < 6; ++k) tp[7 * s + k] = y[k];
-        tp[7 * s + 6] = lnw;
     }
-    void get(int s, double y[6], double& lnw) const
+    void put_lnw(int s, double lnw) { tp[7 * s + 6] = lnw; }
+    void get(int s, double y[6]) const
     {
         for (int k = 0; k < 6; ++k) y[k] = tp[7 * s + k];
-        lnw = tp[7 * s + 6];
     }
+    double get_lnw(int s) const { return tp[7 * s + 6]; }
 };
 
 struct HostSamples {
