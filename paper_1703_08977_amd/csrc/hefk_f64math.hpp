@@ -3,9 +3,9 @@
 // a root is taken), without the special-case handling of a general library:
 //
 //   log(x)      x = m 2^e, m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s),
-//               s = (m - 1)/(m + 1), |s| <= 0.1716, by its Taylor series to s^23.
+//               s = (m - 1)/(m + 1), |s| <= 0.1716, by its Taylor series to s^21.
 //   sincos(2 pi u), u in [0, 1): x = 2u = k/2 + y, |y| <= 1/4, t = pi y,
-//               Taylor series of sin t to t^17 and cos t to t^18, quadrant k mod 4.
+//               Taylor series of sin t to t^17 and cos t to t^16, quadrant k mod 4.
 //   exp(x)      x <= 0: x = k ln 2 + r, |r| <= ln2/2 (two-part ln 2), Taylor series
 //               of e^r to r^13, then 2^k by exponent scaling.
 //   expm1(x)    x <= 0: the same reduction, e^r - 1 by its series, 2^k (e^r - 1) + 2^k - 1.
@@ -114,9 +114,8 @@ HD double log_scaled(double x, double e_off)
     e = big ? e + 1 : e;
     const double s = (m - 1.0) * rcp_nz(m + 1.0);
     const double z = s * s;
-    // sum_{k=0}^{11} z^k / (2k + 1)
-    double p = 1.0 / 23.0;
-    p = ::fma(p, z, 1.0 / 21.0);
+    // sum_{k=0}^{10} z^k / (2k + 1); the next term, z^11 / 23 <= 7e-19, is below the rounding
+    double p = 1.0 / 21.0;
     p = ::fma(p, z, 1.0 / 19.0);
     p = ::fma(p, z, 1.0 / 17.0);
     p = ::fma(p, z, 1.0 / 15.0);
@@ -166,9 +165,8 @@ HD void sincos2pi(double u, double* s_out, double* c_out)
     ps = ::fma(ps, z, 1.0 / 120.0);              // + 1/5!
     ps = ::fma(ps, z, -1.0 / 6.0);               // - 1/3!
     const double sn = ::fma(t * z, ps, t);
-    // cos t = 1 + sum_{j=1}^{9} (-1)^j z^j / (2j)!
-    double pc = -1.0 / 6402373705728000.0;       // - 1/18!
-    pc = ::fma(pc, z, 1.0 / 20922789888000.0);   // + 1/16!
+    // cos t = 1 + sum_{j=1}^{8} (-1)^j z^j / (2j)!; the next term, t^18 / 18! <= 3e-18, is below the rounding
+    double pc = 1.0 / 20922789888000.0;          // + 1/16!
     pc = ::fma(pc, z, -1.0 / 87178291200.0);     // - 1/14!
     pc = ::fma(pc, z, 1.0 / 479001600.0);        // + 1/12!
     pc = ::fma(pc, z, -1.0 / 3628800.0);         // - 1/10!

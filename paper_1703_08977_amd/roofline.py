@@ -20,7 +20,7 @@ included, issue at 0.250 wave-instructions per SIMD-cycle -- one slot per
 cycle (a wave64 instruction holds a 16-lane SIMD for 4 clocks).  They are
 also reported apart.  Binary64 library functions count their
 polynomial and range-reduction operations: sqrt 8, division 10, exp 20,
-expm1 24, -2 log 26, sincospi 35.  Counts follow the formulas term by term
+expm1 24, -2 log 25, sincospi 34.  Counts follow the formulas term by term
 (they are not read back from the compiled code).
 """
 from __future__ import annotations
@@ -42,8 +42,8 @@ PHILOX_BLOCK = 10 * (2 + 2) - 3 - 1
 # binary32 the series to x^7 beside e^x - 1 and a select, binary64 the reduced series.
 F32 = {"sqrt": (0, 1), "rcp": (0, 1), "dist": (1, 1), "exp": (1, 1), "expm1": (11, 1), "log": (1, 1),
        "sincos": (0, 2)}
-F64 = {"sqrt": (8, 0), "rcp": (10, 0), "dist": (18, 0), "exp": (20, 0), "expm1": (24, 0), "log": (26, 0),
-       "sincos": (35, 0)}
+F64 = {"sqrt": (8, 0), "rcp": (10, 0), "dist": (18, 0), "exp": (20, 0), "expm1": (24, 0), "log": (25, 0),
+       "sincos": (34, 0)}
 
 
 class _Count:
