@@ -55,11 +55,7 @@ HD double neg2log_(double x) { return f64::neg2log(x); }
 // the logarithm whose base the Box-Muller radius scale assumes: natural in binary64
 HD double logb_(double x) { return f64::log_normal(x); }
 // r = sqrt(q) and 1/r of a squared distance q > 0
-HD void dist_inv(double q, double& r, double& i)
-{
-    r = f64::sqrt_pos(q);
-    i = f64::rcp_nz(r);
-}
+HD void dist_inv(double q, double& r, double& i) { f64::dist_inv(q, r, i); }
 // sin(2 pi u), cos(2 pi u) for u in (0, 1)
 HD void sincos2pi(double u, double* s, double* c) { f64::sincos2pi(u, s, c); }
 

@@ -12,6 +12,8 @@
 //   sqrt(x)     x >= 0: y ~ 1/sqrt(x) from the hardware seed, two Newton steps on
 //               g = x y, h = y/2 (Goldschmidt's coupled iteration), x = 0 -> 0.
 //   1/x         hardware reciprocal seed and two Newton steps, x = 0 -> inf.
+//   sqrt and 1/sqrt of a squared distance together: the square root's iteration, then one
+//               Newton step on its reciprocal half.
 // sqrt_pos, rcp_nz and log_normal are the same arithmetic without the tests for
 // zero and subnormal arguments: the walker step calls them where its arguments
 // cannot be zero (a uniform of the noise, 1 + ..., a distance), and an argument
@@ -93,6 +95,21 @@ HD double sqrt_pos(double x)
     const double d = ::fma(-g, g, x);
     g = ::fma(d, h, g);
     return g;
+}
+
+// r = sqrt(q) and i = 1/r for finite q > 0 from one reciprocal square root seed: the coupled
+// iteration of sqrt_pos gives r, and i = 2h, Newton-refined once against the final r
+HD void dist_inv(double q, double& r, double& i)
+{
+    const double y = rsq_seed(q);
+    double g = q * y, h = 0.5 * y;
+    const double e = ::fma(-g, h, 0.5);
+    g = ::fma(g, e, g);
+    h = ::fma(h, e, h);
+    const double d = ::fma(-g, g, q);
+    r = ::fma(d, h, g);
+    const double i0 = 2.0 * h;
+    i = ::fma(i0, ::fma(-r, i0, 1.0), i0);
 }
 
 // sqrt(x), x >= 0

@@ -18,10 +18,10 @@ issue slots like the rest: the hardware counters count them among the VALU
 instructions, and over the mixed P_z step those instructions, transcendentals
 included, issue at 0.250 wave-instructions per SIMD-cycle -- one slot per
 cycle (a wave64 instruction holds a 16-lane SIMD for 4 clocks).  They are
-also reported apart.  Binary64 library functions count their
-polynomial and range-reduction operations: sqrt 8, division 10, exp 20,
-expm1 24, -2 log 25, sincospi 34.  Counts follow the formulas term by term
-(they are not read back from the compiled code).
+also reported apart.  Binary64 functions count their polynomial and
+range-reduction operations (the table F64 below), a binary64 select as two
+32-bit selects.  Counts follow the formulas term by term (they are not read
+back from the compiled code).
 """
 from __future__ import annotations
 
@@ -42,8 +42,17 @@ PHILOX_BLOCK = 10 * (2 + 2) - 3 - 1
 # binary32 the series to x^7 beside e^x - 1 and a select, binary64 the reduced series.
 F32 = {"sqrt": (0, 1), "rcp": (0, 1), "dist": (1, 1), "exp": (1, 1), "expm1": (11, 1), "log": (1, 1),
        "sincos": (0, 2)}
-F64 = {"sqrt": (8, 0), "rcp": (10, 0), "dist": (18, 0), "exp": (20, 0), "expm1": (24, 0), "log": (25, 0),
-       "sincos": (34, 0)}
+# binary64 (hefk_f64math.hpp, counted from the code, a binary64 select as two 32-bit selects):
+# sqrt  = seed, coupled iteration, correction (8); rcp = seed + two Newton steps (5);
+# dist  = seed, the coupled iteration of sqrt, one Newton step on 1/r (11);
+# exp   = reduction (4), 13 series terms, 2^k and the underflow guard (22);
+# expm1 = reduction (4), 11 series terms, e^r - 1 from r (2), 2^k, 2^k - 1, guard and fused sum (24);
+# log   = exponent and mantissa fields (3), halving above sqrt 2 (5), s = (m - 1)/(m + 1) (8), z (1),
+#         10 series terms (9), 2 s (1 + z p) (3), the exponent's two-part ln 2 (3), times -2 dt (1): 34;
+# sincos = quadrant reduction (5), t^2 (1), sin series (9), cos series (8), quadrant selects and
+#         signs (16): 39
+F64 = {"sqrt": (8, 0), "rcp": (5, 0), "dist": (11, 0), "exp": (22, 0), "expm1": (24, 0), "log": (34, 0),
+       "sincos": (39, 0)}
 
 
 class _Count:
@@ -99,9 +108,9 @@ def _trial(c: _Count, f, trial: str):
         # E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + A u' cos + the Jastrow radial part (5)
         c.ops(2 + 1 + drift + 3 + 5)
         return
-    # d = (A - a)(r1 - r2) (2), its sign (1), the pair (t1, t2) (2); the argument -|d| is an
-    # operand modifier in binary32 and a select in binary64
-    c.ops(2 + 1 + 2 + (1 if f is F64 else 0))
+    # d = (A - a)(r1 - r2) (2), its sign (1), the pair (t1, t2) (2 selects); the argument -|d| is
+    # an operand modifier in binary32 and a select in binary64, where a select takes two slots
+    c.ops(2 + 1 + 2 if f is F32 else 2 + 1 + 4 + 2)
     if trial == "triplet":
         c.fn(f, "expm1")
         c.fn(f, "rcp")

@@ -18,7 +18,7 @@ int main()
 {
     std::mt19937_64 rng(7);
     std::uniform_real_distribution<double> U(0.0, 1.0);
-    double e_log = 0, e_sin = 0, e_cos = 0, e_exp = 0, e_sqrt = 0, e_rcp = 0, e_expm1 = 0, e_expm1f = 0;
+    double e_log = 0, e_sin = 0, e_cos = 0, e_exp = 0, e_sqrt = 0, e_rcp = 0, e_expm1 = 0, e_expm1f = 0, e_dr = 0, e_di = 0;
     long same = 0, total = 0;
     for (int i = 0; i < 2000000; ++i) {
         const double u = (std::floor(U(rng) * 4294967296.0) + 0.5) * 0x1p-32;  // the uniforms of the step
@@ -36,6 +36,11 @@ int main()
         const double xs = x * x;
         e_sqrt = std::fmax(e_sqrt, ulp_err(hefk::f64::sqrt(xs), std::sqrt(xs)));
         e_rcp = std::fmax(e_rcp, ulp_err(hefk::f64::rcp(x), 1.0 / x));
+        // distance and its reciprocal together, against the correctly rounded sqrt and 1/sqrt (long double)
+        double dr, di;
+        hefk::f64::dist_inv(xs, dr, di);
+        e_dr = std::fmax(e_dr, ulp_err(dr, std::sqrt(xs)));
+        e_di = std::fmax(e_di, ulp_err(di, (double)(1.0L / std::sqrt((long double)xs))));
         // e^x - 1 for x <= 0: uniform over [-40, 0] and log-uniform over [-1, -1e-12]
         const double xm = (i & 1) ? -U(rng) * 40.0 : -std::exp(-U(rng) * 27.6);
         e_expm1 = std::fmax(e_expm1, ulp_err(hefk::f64::expm1_neg(xm), std::expm1(xm)));
@@ -49,8 +54,9 @@ int main()
         same += hefk::f64::rcp_nz(x) == hefk::f64::rcp(x);
         same += hefk::f64::log_normal(u) == hefk::f64::log(u);
     }
-    std::printf("log %.3f sin %.3f cos %.3f exp %.3f sqrt %.3f rcp %.3f expm1 %.3f same %.6f expm1f %.3g\n", e_log,
-                e_sin, e_cos, e_exp, e_sqrt, e_rcp, e_expm1, (double)same / (double)total, e_expm1f);
+    std::printf("log %.3f sin %.3f cos %.3f exp %.3f sqrt %.3f rcp %.3f expm1 %.3f same %.6f expm1f %.3g dist %.3f "
+                "idist %.3f\n", e_log, e_sin, e_cos, e_exp, e_sqrt, e_rcp, e_expm1, (double)same / (double)total, e_expm1f,
+                e_dr, e_di);
     std::printf("special %g %g %g %g %g %g\n", hefk::f64::log(0.0), hefk::f64::sqrt(0.0), hefk::f64::rcp(0.0),
                 hefk::f64::exp(-800.0), hefk::f64::expm1_neg(0.0), hefk::f64::expm1_neg(-800.0));
     return 0;

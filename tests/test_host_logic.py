@@ -273,6 +273,7 @@ def test_binary64_step_functions_against_the_c_library():
     assert err["sin"] <= 2.0 and err["cos"] <= 2.0, err   # absolute, in units of 2^-53
     assert err["expm1"] <= 2.0 and err["same"] == 1.0, err
     assert err["expm1f"] < 3e-7, err  # binary32: a few units of 2^-24 relative
+    assert err["dist"] <= 1.0 and err["idist"] <= 1.5, err
     assert out[1].split()[1:] == ["-inf", "0", "inf", "0", "0", "-1"]
 
 
