@@ -613,13 +613,16 @@ HD void init_walker(const TrialParams<double>& tp, const Stream& st, int n_met, 
     for (int k = 0; k < 6; ++k) y[k] = init_sigma * xi[k];
     double lp = trial_lnpsi<TRIAL>(tp, y);
     const double h = 1.7320508075688772 * sigma_m;  // sqrt(3) sigma: the box of standard deviation sigma
+    // displacement h (2 v - 1), v = (f + 1/2) 2^-16, as (h 2^-16) (2 f - 65535): an exact
+    // integer times an exact power-of-two multiple of h
+    const double hs = h * 0x1p-16;
     for (int mstep = 0; mstep < n_met; ++mstep) {
         const Words w = st.block(PHASE_METROPOLIS, (uint32_t)mstep);
         double yt[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const uint32_t f = (w.w[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
-            yt[k] = y[k] + h * (2.0 * (((double)f + 0.5) * 0x1p-16) - 1.0);
+            yt[k] = m::fma_(hs, (double)((int32_t)(2u * f) - 65535), y[k]);
         }
         const double u = unit32(w.w[3], 0.0);
         const double lpt = trial_lnpsi<TRIAL>(tp, yt);
