@@ -194,11 +194,12 @@ HD void sincos2pi(double u, double* s_out, double* c_out)
     const double cs = ::fma(z, pc, 1.0);
     // angle = k pi/2 + t: odd quadrants exchange sin and cos; sin is negated in
     // quadrants 2, 3 and cos in quadrants 1, 2 (selects, no branches)
-    const int q = ((int)k) & 3;
-    const double a = (q & 1) ? cs : sn;
-    const double b = (q & 1) ? sn : cs;
-    *s_out = (q & 2) ? -a : a;
-    *c_out = ((q + 1) & 2) ? -b : b;
+    const uint32_t q = (uint32_t)(int)k;
+    const double a = (q & 1u) ? cs : sn;
+    const double b = (q & 1u) ? sn : cs;
+    // the sign flips as xors of the sign bit: bit 1 of q for sin, of q + 1 for cos
+    *s_out = from_bits(bits(a) ^ ((uint64_t)(q & 2u) << 62));
+    *c_out = from_bits(bits(b) ^ ((uint64_t)((q + 1u) & 2u) << 62));
 }
 
 // e^x for x <= 0 (and moderate x > 0)

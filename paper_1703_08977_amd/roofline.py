@@ -49,10 +49,10 @@ F32 = {"sqrt": (0, 1), "rcp": (0, 1), "dist": (1, 1), "exp": (1, 1), "expm1": (1
 # expm1 = reduction (4), 11 series terms, e^r - 1 from r (2), 2^k, 2^k - 1, guard and fused sum (24);
 # log   = exponent and mantissa fields (3), halving above sqrt 2 (5), s = (m - 1)/(m + 1) (8), z (1),
 #         10 series terms (9), 2 s (1 + z p) (3), the exponent's two-part ln 2 (3), times -2 dt (1): 34;
-# sincos = quadrant reduction (5), t^2 (1), sin series (9), cos series (8), quadrant selects and
-#         signs (16): 39
+# sincos = quadrant reduction (5), t^2 (1), sin series (9), cos series (8), the quadrant's
+#         exchange (5) and its sign bits (7): 35
 F64 = {"sqrt": (8, 0), "rcp": (5, 0), "dist": (11, 0), "exp": (22, 0), "expm1": (24, 0), "log": (34, 0),
-       "sincos": (39, 0)}
+       "sincos": (35, 0)}
 
 
 class _Count:
