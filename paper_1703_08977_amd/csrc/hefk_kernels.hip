@@ -25,6 +25,23 @@ constexpr int kBlock = 256;  // 4 waves of 64 lanes; one walker per lane
 #ifndef HEFK_WAVES_F64
 #define HEFK_WAVES_F64 4
 #endif
+// The kernels with the variant flags (plain walk, node bridge) carry both variants'
+// code in their step loop.  For the trial functions with an angular factor or a
+// second orbital that loop spills at the budgets above, and fewer, wider waves win.
+#ifndef HEFK_WAVES_F32_EXT
+#define HEFK_WAVES_F32_EXT 4
+#endif
+#ifndef HEFK_WAVES_F64_EXT
+#define HEFK_WAVES_F64_EXT 3
+#endif
+
+template <typename R, int TRIAL, bool EXT>
+constexpr int propagate_waves()
+{
+    constexpr bool heavy = EXT && TRIAL != TRIAL_EXPO && TRIAL != TRIAL_PADE;
+    if (sizeof(R) == 4) return heavy ? HEFK_WAVES_F32_EXT : HEFK_WAVES_F32;
+    return heavy ? HEFK_WAVES_F64_EXT : HEFK_WAVES_F64;
+}
 
 struct KArgs {
     TrialParams<double> tpd;
@@ -124,7 +141,7 @@ __device__ __forceinline__ void sample_row(const KArgs& a, double* part_row, boo
 }
 
 template <typename R, int TRIAL, int NOISE, bool EXT>
-__global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? HEFK_WAVES_F32 : HEFK_WAVES_F64) void propagate_kernel(
+__global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void propagate_kernel(
     const KArgs a)
 {
     __shared__ double red[kRedSlots];
