@@ -109,13 +109,47 @@ KERNEL_SOURCES = ["include/he_fk.h", "paper_1703_08977_amd/csrc/hefk_device.hpp"
 COUNTERS = os.path.join(ROOT, "profiles", "propagate_pz_16m_counters.txt")
 
 
+def _code_tokens(text: str) -> str:
+    """C/C++ source with comments removed and each run of whitespace folded to one
+    space: edits to comments or layout leave the compiled kernel, and so the digest, as
+    they were.  String and character literals are kept verbatim."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+            c = " "
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            c = " "
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+            continue
+        else:
+            i += 1
+        if not c.isspace():
+            out.append(c)
+        elif out and out[-1] != " ":
+            out.append(" ")
+    return "".join(out).strip()
+
+
 def source_digest() -> str:
-    """sha256 over the sources of the propagate kernel and its build flags."""
+    """sha256 over the code of the propagate kernel's sources (comments and layout
+    excluded) and its build script (verbatim: it holds the compiler flags)."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(rel.encode() + b"\0" + f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = f.read()
+        body = text if rel.endswith(".py") else _code_tokens(text)
+        h.update(rel.encode() + b"\0" + body.encode())
     return h.hexdigest()
 
 

@@ -16,9 +16,10 @@ namespace hefk {
 constexpr int kBlock = 256;  // 4 waves of 64 lanes; one walker per lane
 
 // Minimum resident waves per SIMD the propagate kernels are compiled for
-// (register budget 512 / waves).  Both steps keep their loops free of spills at
-// these budgets (80 registers in binary32, 128 in binary64); the spills that remain
-// are in the sampling code, run once per sampling interval.
+// (register budget 512 / waves: 80 registers in binary32, 128 in binary64).  At these
+// budgets the step loops with Gaussian increments have no spills, and those of the +-1
+// walk keep at most two scratch accesses per step; the other spills are in the sampling
+// code, run once per sampling interval.
 #ifndef HEFK_WAVES_F32
 #define HEFK_WAVES_F32 6
 #endif

@@ -289,3 +289,22 @@ def test_bench_reports_committed_traffic_only_for_the_profiled_configuration():
     assert bench.committed_traffic(W.get("he_2tripS_4m")) is None
     t = bench.committed_traffic(W.get("he_2P_pz_16m"))
     assert t is None or 1e9 < t < 1e10
+
+
+def test_source_digest_ignores_comments_and_layout_only():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod2", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    tok = bench._code_tokens
+    base = 'int f(int a) {\n  return a * 2; // double it\n}\nconst char* s = "a // b";\n'
+    # comments (line and block) and whitespace runs do not count
+    assert tok(base) == tok('int f(int a) { /* note */ return a * 2;\n\n}\nconst char* s = "a // b";')
+    # a comment marker inside a string or character literal is code
+    assert '"a // b"' in tok(base)
+    assert tok("char c = '/'; int x;") == "char c = '/'; int x;"
+    assert tok('const char* q = "\\"/*\\""; int y;').endswith("int y;")
+    # any change to the code does
+    assert tok(base) != tok(base.replace("a * 2", "a * 3"))
+    assert tok(base) != tok(base.replace('"a // b"', '"a //  b"'))
