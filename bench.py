@@ -36,13 +36,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16384)
     ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle", "grad"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle", "grad", "cases"],
                     help="copy: a plain 1 GiB device copy, three times (the reference reading of the HBM "
                          "byte counters FETCH_SIZE / WRITE_SIZE); oracle: time the CPU oracle alone on the "
                          "4096-walker ground state in full and on walkers 0..65535 of the Pade ground state "
                          "at dt = 0.002; grad: the pathwise gradient of E(T = 2) for the Pade-Jastrow trial, "
                          "2^18 walkers x 1000 steps (forward with checkpoints, then he_fk_grad), with the "
-                         "oracle's gradient timed beside it")
+                         "oracle's gradient timed beside it; cases: propagate throughput of the other "
+                         "trials, noises, precisions and the variant kernels (plain walk, node bridge) "
+                         "at 2^24 walkers")
     return ap.parse_args()
 
 
@@ -283,6 +285,57 @@ def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu):
     print(json.dumps(out), flush=True)
 
 
+# (label, workload, overrides, timed steps): every propagate kernel family at 2^24 walkers
+CASES = [
+    ("P_z, mixed", "he_2P_pz_16m", {}, 4000),
+    ("P_z, FP64", "he_2P_pz_16m", {"precision": "fp64"}, 2000),
+    ("P_z, +-1 walk, mixed", "he_2P_pz_16m", {"noise": "pm1"}, 4000),
+    ("triplet, mixed", "he_2tripS_4m", {"n_walkers": 1 << 24}, 4000),
+    ("triplet, FP64", "he_2tripS_4m", {"n_walkers": 1 << 24, "precision": "fp64"}, 2000),
+    ("fn 5 (+-1 walk, right end-point sum), mixed", "he_2tripS_fn5_1m", {"n_walkers": 1 << 24}, 4000),
+    ("Pade-Jastrow, FP64", "he_1s_pade_1m", {"n_walkers": 1 << 24, "dt": 0.002}, 2000),
+    ("Pade-Jastrow, plain walk, mixed", "he_1s_pade_1m",
+     {"n_walkers": 1 << 24, "dt": 0.002, "plain": True, "precision": "mixed", "contract": 2}, 2000),
+    ("P_z + bridge, mixed", "he_2P_pz_16m", {"bridge": True}, 2000),
+    ("triplet + bridge, mixed", "he_2tripS_4m", {"n_walkers": 1 << 24, "bridge": True}, 2000),
+    ("fn 7 + bridge, plain walk, mixed", "he_2P_fn7_1m", {"n_walkers": 1 << 24, "bridge": True, "plain": True},
+     2000),
+    ("P_z + bridge, FP64", "he_2P_pz_16m", {"bridge": True, "precision": "fp64"}, 1000),
+    ("triplet + bridge, FP64", "he_2tripS_4m", {"n_walkers": 1 << 24, "bridge": True, "precision": "fp64"}, 1000),
+    ("fn 7 + bridge, plain walk, FP64", "he_2P_fn7_1m",
+     {"n_walkers": 1 << 24, "bridge": True, "plain": True, "precision": "fp64"}, 1000),
+]
+
+
+def cases_bench(reps):
+    """Propagate throughput per kernel family: start ensemble, 200 untimed steps, then
+    `reps` timed propagations of each case's step count (HIP events on the launch
+    stream), sampling every 100 steps; the median rate is reported."""
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    from paper_1703_08977_amd import workloads as W
+    rows = []
+    for label, name, over, n_steps in CASES:
+        cfg = W.get(name, n_steps=n_steps, sample_every=100, **over)
+        ens = Ensemble(cfg).init()
+        ens.propagate(0, 200, 100)
+        rates = []
+        for _ in range(max(1, reps)):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            ens.propagate(0, n_steps, 100)
+            ev[1].record()
+            torch.cuda.synchronize()
+            rates.append(cfg["n_walkers"] * n_steps / (ev[0].elapsed_time(ev[1]) / 1e3))
+        rates.sort()
+        rows.append({"case": label, "workload": name, "n_walkers": cfg["n_walkers"], "n_steps": n_steps,
+                     "precision": cfg["precision"], "walker_steps_per_s": rates[len(rates) // 2]})
+        print("%-44s %.3e walker-steps/s" % (label, rows[-1]["walker_steps_per_s"]), file=sys.stderr, flush=True)
+        del ens
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "cases", "reps": reps, "cases": rows}), flush=True)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -296,6 +349,10 @@ def cpu_model() -> str:
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "
+              "reduction, and this benchmark measures one MI355X (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
     if args.mode == "copy":
         copy_reference()
         return
@@ -305,10 +362,9 @@ def main():
     if args.mode == "grad":
         grad_bench(args.steps, args.warmup, args.cpu_walkers, args.no_cpu_baseline)
         return
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the walkers of this method share nothing but the per-sample "
-              "reduction, and this benchmark measures one MI355X (requested --gpus %d)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+    if args.mode == "cases":
+        cases_bench(args.steps)
+        return
     import torch
     from paper_1703_08977_amd import workloads as W
     from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, fp32_flops_per_walker_step, slots_per_walker_step,

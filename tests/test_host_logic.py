@@ -308,3 +308,22 @@ def test_source_digest_ignores_comments_and_layout_only():
     # any change to the code does
     assert tok(base) != tok(base.replace("a * 2", "a * 3"))
     assert tok(base) != tok(base.replace('"a // b"', '"a //  b"'))
+
+
+def test_bench_cases_cover_every_trial_family_and_both_precisions():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod3", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    seen = set()
+    for label, name, over, n_steps in bench.CASES:
+        cfg = W.get(name, n_steps=n_steps, sample_every=100, **over)
+        assert cfg["n_walkers"] == 1 << 24 and n_steps % 100 == 0, label
+        seen.add((cfg["trial"], cfg["precision"], bool(cfg.get("plain")), bool(cfg.get("bridge"))))
+    trials = {t for t, _, _, _ in seen}
+    assert {"pz", "triplet", "triplet_r0", "pade", "pz_sum"} <= trials
+    assert {p for _, p, _, _ in seen} == {"mixed", "fp64"}
+    # the variant kernels (plain walk, node bridge) are timed in both precisions
+    assert any(pl or br for _, p, pl, br in seen if p == "mixed")
+    assert any(pl or br for _, p, pl, br in seen if p == "fp64")
