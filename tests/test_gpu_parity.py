@@ -288,6 +288,26 @@ def test_full_size_triplet_fp64():
     _last_row_property(g)
 
 
+# The variant kernels (node bridge, plain walk) have register budgets of their own, so their
+# grids differ from the bench kernel's: full walker count, shorter runs.
+@pytest.mark.parametrize("name,over", [
+    ("he_2P_pz_16m", dict(bridge=True, n_steps=2000)),
+    ("he_2P_fn7_1m", dict(n_walkers=1 << 24, bridge=True, plain=True, n_steps=1800)),
+], ids=["pz_bridge", "fn7_bridge_plain"])
+def test_full_size_variant_kernels_fp64(name, over):
+    cfg, g, r, ids = _full_size(name, precision="fp64", **over)
+    gg = {k: g[k][ids] for k in ("x0", "x", "lnw")}
+    _compare(gg, r, node=True)
+    _last_row_property(g)
+
+
+def test_full_size_variant_kernel_mixed_last_row():
+    cfg = W.get("he_2tripS_4m", n_walkers=1 << 24, bridge=True, n_steps=2000)
+    g = gpu_run(cfg)
+    _last_row_property(g)
+    assert g["samples"][-1, 5] == 0
+
+
 def test_full_size_pz_mixed_last_row():
     cfg = W.get("he_2P_pz_16m")
     g = gpu_run(cfg)
