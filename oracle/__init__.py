@@ -63,7 +63,7 @@ def lib():
         L.ofk_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.ofk_init.argtypes = [pp, u64p, ctypes.c_int64, dp, dp]
         L.ofk_propagate.argtypes = [pp, u64p, ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ctypes.c_int64,
-                                    ctypes.c_int64, dp, dp]
+                                    ctypes.c_int64, dp, dp, dp]
         L.ofk_tuples.argtypes = [dp, dp, ctypes.c_int64, ctypes.c_int64, dp]
         L.ofk_dlnw_dtheta.argtypes = [pp, u64p, ctypes.c_int64, dp, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int, dp, ip]
@@ -182,8 +182,10 @@ def init(cfg, ids):
     return x, el
 
 
-def propagate(cfg, ids, x, lnw, step0, n_steps, sample_every, record=True):
-    """Advance walkers (copies); returns (x, lnw, el, ell[n,ns], els[n,ns])."""
+def propagate(cfg, ids, x, lnw, step0, n_steps, sample_every, record=True, node_dmin=False):
+    """Advance walkers (copies); returns (x, lnw, el, ell[n,ns], els[n,ns]), and with
+    ``node_dmin`` also the smallest node-distance estimate 1/|grad ln|Phi|| each walker's
+    path held while alive ([n], a diagnostic)."""
     ids = _ids(ids)
     n = ids.size
     x = np.ascontiguousarray(x, dtype=np.float64).copy()
@@ -192,9 +194,12 @@ def propagate(cfg, ids, x, lnw, step0, n_steps, sample_every, record=True):
     ns = n_steps // sample_every + 1
     ell = np.zeros((n, ns)) if record else None
     els = np.zeros((n, ns)) if record else None
+    dmin = np.zeros(n) if node_dmin else None
     lib().ofk_propagate(ctypes.byref(params(cfg)), _ptr(ids, ctypes.c_uint64), n, _ptr(x), _ptr(lnw), _ptr(el),
                         step0, n_steps, sample_every, _ptr(ell) if record else None,
-                        _ptr(els) if record else None)
+                        _ptr(els) if record else None, _ptr(dmin) if node_dmin else None)
+    if node_dmin:
+        return x, lnw, el, ell, els, dmin
     return x, lnw, el, ell, els
 
 
@@ -214,7 +219,7 @@ def run(cfg, ids, n_steps, sample_every):
     lnw0 = np.zeros(len(x0))
     x, lnw, el, ell, els = propagate(cfg, ids, x0, lnw0, 0, n_steps, sample_every)
     return {"x0": x0, "el0": el0, "x": x, "lnw": lnw, "el": el, "ell": ell, "els": els,
-            "samples": tuples(ell, els)}
+            "samples": tuples(ell, els), "n_steps": n_steps, "sample_every": sample_every}
 
 
 def dlnw_dtheta(cfg, ids, y0, n_steps, sample_every, direction):

@@ -480,10 +480,13 @@ static double bridge_log_survival(const ofk_params* p, double g2a, double g2b)
  * walkers) and e(Y) = V(Y) - e_ref; the start ensemble and the node test still
  * come from the trial function.  The drift limiting does not apply to it.
  * ell_s / el_s (may be NULL) receive lnw and E_L at steps step0 + s*sample_every.
+ * node_dmin (may be NULL; a diagnostic, no part of the method) receives the smallest
+ * node-distance estimate 1/|grad ln|Phi|| over the positions the walker held while
+ * alive: the start and every accepted step (not the first position across the node).
  */
 void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* lnw, double* el_io,
                           int64_t step0, int64_t n_steps, int64_t sample_every,
-                          double* ell_s, double* el_s)
+                          double* ell_s, double* el_s, double* node_dmin)
 {
     const int plain = (p->flags & OFK_FLAG_PLAIN) != 0;
     const int bridge = (p->flags & OFK_FLAG_BRIDGE) != 0;
@@ -495,6 +498,7 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
     double sqdt = sqrt(p->dt);
     int node = trial_has_node(p);
     int64_t s = 0;
+    double dmin = 1.0 / sqrt(cur.gphi2);
     if (ell_s) ell_s[s] = w;
     if (el_s) el_s[s] = cur.el;
     ++s;
@@ -525,6 +529,7 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
                 cur = nxt;
                 f = fn;
                 eb = ebn;
+                if (1.0 / sqrt(cur.gphi2) < dmin) dmin = 1.0 / sqrt(cur.gphi2);
             }
         }
         if (sample_every > 0 && (k + 1) % sample_every == 0) {
@@ -535,17 +540,21 @@ void ofk_propagate_walker(const ofk_params* p, uint64_t g, double y[6], double* 
     }
     *lnw = w;
     if (el_io) *el_io = cur.el;
+    if (node_dmin) *node_dmin = dmin;
 }
 
-/* Many walkers: x [n][6], lnw [n], el [n]; ell / els [n][n_samples] or NULL. */
+/* Many walkers: x [n][6], lnw [n], el [n]; ell / els [n][n_samples] or NULL;
+   node_dmin [n] or NULL (the diagnostic of ofk_propagate_walker). */
 void ofk_propagate(const ofk_params* p, const uint64_t* ids, int64_t n, double* x, double* lnw, double* el,
-                   int64_t step0, int64_t n_steps, int64_t sample_every, double* ell, double* els)
+                   int64_t step0, int64_t n_steps, int64_t sample_every, double* ell, double* els,
+                   double* node_dmin)
 {
     int64_t ns = (sample_every > 0) ? n_steps / sample_every + 1 : 1;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         ofk_propagate_walker(p, ids[i], x + 6 * i, lnw + i, el + i, step0, n_steps, sample_every,
-                             ell ? ell + ns * i : NULL, els ? els + ns * i : NULL);
+                             ell ? ell + ns * i : NULL, els ? els + ns * i : NULL,
+                             node_dmin ? node_dmin + i : NULL);
     }
 }
 

@@ -713,3 +713,63 @@ def test_score_weighted_gradients_reduce_to_the_variational_formulas():
         ref_v = np.mean(2 * dev * de) + np.mean((dev ** 2 - np.mean(dev ** 2)) * (s - s.mean()))
         assert abs(g_e[d] - ref_e) < 3e-3 * abs(ref_e), (d, g_e[d], ref_e)
         assert abs(g_v[d] - ref_v) < 3e-3 * abs(ref_v), (d, g_v[d], ref_v)
+
+
+# --------------------------------------------------------------------------
+# The paper's right end-point Riemann sum of the integrand (section "Path
+# Integral Theory": the sum over the walk of V_P at the positions the walk
+# reaches, times 1/n).
+# --------------------------------------------------------------------------
+
+def test_right_end_point_sum_along_the_plain_path():
+    # eq. (2) with the right end-point rule: ln w after k steps is -dt sum_{j=1..k} (V(X_j) - e_ref)
+    # along the Brownian path rebuilt from the noise; the left end-point sum and the trapezoid
+    # differ from it by far more than the tolerance, so a slip to either fails here
+    cfg = W.get("he_1s_pade_1m", dt=0.01, plain=True, quad="right")
+    ids = np.arange(16) * 5 + 1
+    x0, _ = oracle.init(cfg, ids)
+    n = 12
+    x, _, _, ell, _ = oracle.propagate(cfg, ids, x0, np.zeros(len(ids)), 0, n, 1)
+    path = [x0]
+    for k in range(n):
+        path.append(path[-1] + math.sqrt(cfg["dt"]) * oracle.noise_bulk(cfg, k, ids))
+    path = np.array(path)
+    assert np.abs(x - path[-1]).max() < 1e-13
+    v = _potential(cfg, path) - cfg["e_ref"]
+    zero = np.zeros((1, len(ids)))
+    right = -np.concatenate([zero, np.cumsum(cfg["dt"] * v[1:], axis=0)])
+    left = -np.concatenate([zero, np.cumsum(cfg["dt"] * v[:-1], axis=0)])
+    trap = -np.concatenate([zero, np.cumsum(0.5 * cfg["dt"] * (v[1:] + v[:-1]), axis=0)])
+    assert np.abs(ell.T - right).max() < 1e-11
+    assert np.abs(ell.T - left).max() > 1e-4 and np.abs(ell.T - trap).max() > 1e-4
+
+
+def test_right_end_point_sum_along_the_drifted_path():
+    # the generalized walk with the limiter: walked one step per call (resume is bitwise), the
+    # weight is -dt sum_j f(Y_j) (E_L(Y_j) - e_ref) over the positions reached, with the limiting
+    # factor in its textbook form f = (sqrt(1 + 2x) - 1)/x, x = a dt |b(Y_j)|^2
+    a, dt = 0.7, 0.01
+    cfg = W.get("he_1s_pade_1m", dt=dt, drift_limit=a, quad="right", e_ref=-2.9)
+    ids = np.arange(8) * 11 + 2
+    x, _ = oracle.init(cfg, ids)
+    lnw = np.zeros(len(ids))
+    expected = np.zeros(len(ids))
+    for k in range(10):
+        x, lnw, el, _, _ = oracle.propagate(cfg, ids, x, lnw, k, 1, 1)
+        for i in range(len(ids)):
+            e = oracle.trial_eval(cfg, x[i])
+            assert abs(e.el - el[i]) < 1e-12
+            xx = a * dt * float(e.b @ e.b)
+            f = (math.sqrt(1 + 2 * xx) - 1) / xx
+            expected[i] -= dt * f * (e.el - cfg["e_ref"])
+    assert np.abs(lnw - expected).max() < 1e-12
+
+
+def test_right_end_point_sum_of_the_exact_system():
+    # Z = 2 without 1/r12 and psi = exp(-2 (r1 + r2)): E_L = -4 everywhere, so with e_ref = 0 the
+    # right end-point sum gives L(t) = 4t exactly, as the trapezoid does
+    cfg = W.get("exact_noee", e_ref=0.0, quad="right")
+    r = oracle.run(cfg, np.arange(512), 200, 20)
+    t = np.arange(11) * 20 * cfg["dt"]
+    assert np.abs(est.log_mean_weight(r["samples"]) - 4.0 * t).max() < 1e-13
+    assert np.abs(r["el"] + 4.0).max() < 1e-12
