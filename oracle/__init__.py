@@ -214,12 +214,13 @@ def tuples(ell, els):
 
 
 def run(cfg, ids, n_steps, sample_every):
-    """Start + propagate from step 0; returns dict with final state and sample tuples."""
+    """Start + propagate from step 0; returns dict with final state, sample tuples and the
+    node-distance diagnostic of each walker's path."""
     x0, el0 = init(cfg, ids)
     lnw0 = np.zeros(len(x0))
-    x, lnw, el, ell, els = propagate(cfg, ids, x0, lnw0, 0, n_steps, sample_every)
+    x, lnw, el, ell, els, dmin = propagate(cfg, ids, x0, lnw0, 0, n_steps, sample_every, node_dmin=True)
     return {"x0": x0, "el0": el0, "x": x, "lnw": lnw, "el": el, "ell": ell, "els": els,
-            "samples": tuples(ell, els), "n_steps": n_steps, "sample_every": sample_every}
+            "samples": tuples(ell, els), "n_steps": n_steps, "sample_every": sample_every, "node_dmin": dmin}
 
 
 def dlnw_dtheta(cfg, ids, y0, n_steps, sample_every, direction):

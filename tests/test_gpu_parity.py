@@ -5,12 +5,16 @@ per sample row |dL| <= 1e-12 max(1, |L|) -- the two sides differ only in
 the rounding of transcendental functions (device math library vs glibc) and
 in fused multiply-adds; absorption decisions must agree exactly.
 
-Trials with a node: the drift grows as 1/(distance to the node), so the
-Euler map amplifies a one-ulp difference for a walker that passes close to
-it (the host build of the same kernel code, which shares glibc with the
-oracle, agrees to 1e-14 on every walker).  There at least 99.9 % of the
-walkers must agree to 1e-12 and every walker to 1e-9; the sample rows keep
-the 1e-12 bound.
+Trials with a node: the drift grows as 1/d with the distance d to the node,
+so one Euler step multiplies a rounding difference by about dt/d^2 (2.5e4
+at d = 2e-4 bohr, dt = 0.001).  There at least 99.95 % of the compared
+walkers (at most one walker when fewer than 2000 are compared) must agree
+to 1e-12, and a walker beyond 1e-12 is an outlier only with evidence: it is
+printed with its error, the smallest node-distance estimate 1/|grad ln|Phi||
+along its oracle path and how far a one-ulp change of its start moves the
+oracle's own end point; its path must be among the 1 % of compared paths
+that came closest to the node and within NODE_DMIN of it, and its error
+stays below 1e-9.  The sample rows keep the 1e-12 bound.
 """
 import math
 
@@ -28,25 +32,53 @@ pytestmark = [pytest.mark.gpu,
 TOL = 1e-12
 
 
-NODE_FRAC, NODE_LOOSE = 0.999, 1e-9
+NODE_FRAC, NODE_LOOSE = 0.9995, 1e-9
+# an outlier's oracle path must have come this close to the node (bohr); the median path of
+# the node workloads stays ~0.5 bohr away
+NODE_DMIN = 0.05
+NODE_CLOSEST = 0.01  # ... and be among this fraction of the compared paths closest to the node
 
 
-def _compare(g, r, tol=TOL, node=False):
+def _node_outliers(cfg, ids, r, worst, tol, label):
+    """Outliers of a node trial: print the evidence and check it (see the module docstring)."""
+    bad = np.flatnonzero(worst >= tol)
+    if bad.size == 0:
+        return
+    n_steps, se = r["n_steps"], r["sample_every"]
+    sub = np.asarray(ids, dtype=np.uint64)[bad]
+    dmin = r["node_dmin"]
+    c64 = dict(cfg, precision="fp64")
+    x, lnw, _, _, _ = oracle.propagate(c64, sub, r["x0"][bad], np.zeros(bad.size), 0, n_steps, se, record=False)
+    xp, lp, _, _, _ = oracle.propagate(c64, sub, r["x0"][bad] * (1.0 + 2.0**-52), np.zeros(bad.size), 0,
+                                       n_steps, se, record=False)
+    growth = np.maximum(rel_err(xp, x).max(axis=1), rel_err(lp, lnw))
+    rank = np.argsort(np.argsort(dmin, kind="stable"), kind="stable")  # 0 = the path closest to the node
+    for j, i in enumerate(bad):
+        print("node outlier [%s]: walker %d, error %.3e, min node distance %.2e (rank %d of %d), one-ulp "
+              "start change -> %.2e at the end" % (label, int(sub[j]), worst[i], dmin[i], rank[i], worst.size,
+                                                   growth[j]), flush=True)
+    allowed = max(1, int((1.0 - NODE_FRAC) * worst.size + 1e-9))
+    assert bad.size <= allowed, (label, bad.size, worst.size)
+    assert worst.max() < NODE_LOOSE, (label, worst.max())
+    assert np.all(dmin[bad] < NODE_DMIN), (label, dmin[bad])
+    assert np.all(rank[bad] < max(1.0, NODE_CLOSEST * worst.size)), (label, rank[bad])
+
+
+def _compare(g, r, tol=TOL, node=False, cfg=None, ids=None, label=""):
     # start ensemble
     assert rel_err(g["x0"], r["x0"]).max() < tol
     # absorption agrees walker by walker
     assert np.array_equal(np.isfinite(g["lnw"]), np.isfinite(r["lnw"]))
     alive = np.isfinite(r["lnw"])
-    ex = rel_err(g["x"][alive], r["x"][alive]).max(axis=1) if alive.any() else np.zeros(0)
-    el = rel_err(g["lnw"][alive], r["lnw"][alive])
-    worst = np.maximum(ex, el)
-    if worst.size == 0:  # every walker absorbed: nothing left to compare
+    ex = rel_err(g["x"], r["x"]).max(axis=1)
+    el = rel_err(g["lnw"], r["lnw"])
+    worst = np.where(alive, np.maximum(ex, el), 0.0)
+    if not alive.any():  # every walker absorbed: nothing left to compare
         return ex, el
     if not node:
-        assert worst.max(initial=0.0) < tol, (ex.max(initial=0), el.max(initial=0))
+        assert worst.max(initial=0.0) < tol, (ex[alive].max(initial=0), el[alive].max(initial=0))
     else:
-        assert (worst < tol).mean() >= NODE_FRAC or (worst >= tol).sum() <= 1, np.sort(worst)[-5:]
-        assert worst.max(initial=0.0) < NODE_LOOSE, np.sort(worst)[-5:]
+        _node_outliers(cfg, np.arange(len(worst)) if ids is None else ids, r, worst, tol, label)
     return ex, el
 
 
@@ -96,7 +128,7 @@ def test_parity_ragged(name, over, n):
     cfg = W.get(name, **over)
     g = gpu_run(cfg, n_walkers=n, n_steps=400, sample_every=20)
     r = oracle.run(cfg, np.arange(n), 400, 20)
-    _compare(g, r, node=_has_node(cfg))
+    _compare(g, r, node=_has_node(cfg), cfg=cfg, label="%s %s n=%d" % (name, over, n))
     Lg, Lr = log_mean_weight(g["samples"]), log_mean_weight(r["samples"])
     fin = np.isfinite(Lr)
     assert np.array_equal(fin, np.isfinite(Lg))
@@ -247,11 +279,15 @@ def test_workspace_too_small_is_rejected():
 # summation of every walker's final ln w.
 # --------------------------------------------------------------------------
 
+N_SAMPLED = 10_000
+
+
 def _full_size(name, **over):
     cfg = W.get(name, **over)
+    print("full size: %s %s" % (name, over), flush=True)
     g = gpu_run(cfg)
     rng = np.random.default_rng(2024)
-    ids = np.sort(rng.choice(cfg["n_walkers"], size=48, replace=False))
+    ids = np.sort(rng.choice(cfg["n_walkers"], size=min(N_SAMPLED, cfg["n_walkers"]), replace=False))
     ids[0], ids[-1] = 0, cfg["n_walkers"] - 1
     r = oracle.run(cfg, ids, cfg["n_steps"], cfg["n_steps"])
     return cfg, g, r, ids
@@ -277,14 +313,14 @@ def test_full_size_ground_state_pade_fp64():
 def test_full_size_pz_fp64():
     cfg, g, r, ids = _full_size("he_2P_pz_16m", precision="fp64")
     gg = {k: g[k][ids] for k in ("x0", "x", "lnw")}
-    _compare(gg, r, node=True)
+    _compare(gg, r, node=True, cfg=cfg, ids=ids, label="C5 FP64")
     _last_row_property(g)
 
 
 def test_full_size_triplet_fp64():
     cfg, g, r, ids = _full_size("he_2tripS_4m", precision="fp64")
     gg = {k: g[k][ids] for k in ("x0", "x", "lnw")}
-    _compare(gg, r, node=True)
+    _compare(gg, r, node=True, cfg=cfg, ids=ids, label="C3 FP64")
     _last_row_property(g)
 
 
@@ -297,7 +333,7 @@ def test_full_size_triplet_fp64():
 def test_full_size_variant_kernels_fp64(name, over):
     cfg, g, r, ids = _full_size(name, precision="fp64", **over)
     gg = {k: g[k][ids] for k in ("x0", "x", "lnw")}
-    _compare(gg, r, node=True)
+    _compare(gg, r, node=True, cfg=cfg, ids=ids, label="%s %s" % (name, over))
     _last_row_property(g)
 
 
