@@ -216,14 +216,33 @@ int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0
 /*
  * he_fk_energy: estimators from sample rows (HOST memory, as written by
  * he_fk_propagate and copied back).  Row j is at time t_j = j * dt_sample.
- * aux_out (host, may be NULL): [n_samples][2] = (L_j, S0_j^2 / S2_j) - the log
- * space average and the effective sample size.
+ * aux_out (host, may be NULL): [n_samples][3] = (L_j, S0_j^2 / S2_j, L2_j): the log
+ * space average L = m + ln S0 - ln N (eq. (4)'s ln Z(t)), the effective sample size,
+ * and the log mean square weight L2 = 2 m + ln S2 - ln N (L2 - 2 L = -ln(ESS / N),
+ * the log relative variance of the weights).
  * Errors: EINVAL, ENONFINITE (a row counts non-finite walkers),
  * EALLDEAD (a row has no live walker).  aux_out is filled before these two
  * are reported.
  */
 int he_fk_energy(const double* samples, int64_t n_samples, double dt_sample, double e_ref, int32_t method,
                  const double* fit_w, double* E_out, double* aux_out);
+
+/*
+ * he_fk_energy_blocks: an estimator and its delete-one-group jackknife standard error
+ * from one run.  partials (HOST memory): the per-block partial rows [n_parts][n_samples][8]
+ * that he_fk_propagate leaves in its workspace (each block's rows cover a fixed, disjoint
+ * set of walkers; n_parts = workspace bytes / (64 n_samples)).  The blocks form
+ * G = min(n_groups, n_parts) contiguous groups whose sizes differ by at most one (the
+ * larger first); rows merge by rescaling to the larger maximum, as on the device.  The
+ * statistic: WINDOW the window energy, FIT lambda1 = e_ref - b, FD the energy of the last
+ * sampling interval, MIXED the mixed estimate at the last row (fit_w as for he_fk_energy).
+ * est_out (host) [2]: the statistic of all blocks merged, and
+ * sqrt((G - 1)/G sum_g (x_g - mean x)^2) over the G replicas x_g without group g.
+ * Constraints: n_parts >= 2, n_groups >= 2.
+ * Errors: as he_fk_energy on the merged rows or a replica; EINVAL.
+ */
+int he_fk_energy_blocks(const double* partials, int64_t n_parts, int64_t n_samples, int32_t n_groups,
+                        double dt_sample, double e_ref, int32_t method, const double* fit_w, double* est_out);
 
 /* ---- pathwise gradient (adjoint) ---- */
 #define HE_FK_GRAD_SCORE 1 /* add the derivative of the |psi_T|^2 start law (score term) */

@@ -15,6 +15,8 @@
 namespace {
 
 double log_space_average(const double* r) { return r[0] + log(r[1]) - log(r[6]); }
+// ln of the mean square weight, ln((1/N) sum w^2) = 2 m + ln S2 - ln N
+double log_mean_square(const double* r) { return 2.0 * r[0] + log(r[3]) - log(r[6]); }
 
 // Weighted least squares of y = c0 + c1 x, centred sums; returns 0 on success.
 int wls_line(int64_t n, const double* x, const double* y, const double* w, double* c0, double* c1)
@@ -56,8 +58,9 @@ extern "C" int he_fk_energy(const double* samples, int64_t n_samples, double dt_
         const double* r = samples + 8 * j;
         if (!(r[6] >= 1.0)) return HE_FK_EINVAL;
         if (aux_out) {
-            aux_out[2 * j] = log_space_average(r);
-            aux_out[2 * j + 1] = r[1] * r[1] / r[3];
+            aux_out[3 * j] = log_space_average(r);
+            aux_out[3 * j + 1] = r[1] * r[1] / r[3];
+            aux_out[3 * j + 2] = log_mean_square(r);
         }
         if (r[5] > 0.0)
             status = HE_FK_ENONFINITE;
@@ -115,4 +118,97 @@ extern "C" int he_fk_energy(const double* samples, int64_t n_samples, double dt_
         E_out[1] = c1;
     }
     return HE_FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Error bars from one run: the per-block partial rows of he_fk_propagate cover
+// fixed, disjoint sets of walkers, so groups of blocks are independent
+// sub-ensembles.  Rows merge by rescaling to the larger maximum, as on the device.
+// ---------------------------------------------------------------------------
+namespace {
+
+// acc <- acc (+) r for one sample row (m, S0, S1, S2, n_alive, n_nonfinite, n_total, 0)
+void merge_row(double* acc, const double* r)
+{
+    const double ma = acc[0], mb = r[0];
+    const double m = (mb > ma) ? mb : ma;
+    const double fa = (ma == -INFINITY) ? 0.0 : exp(ma - m);
+    const double fb = (mb == -INFINITY) ? 0.0 : exp(mb - m);
+    acc[0] = m;
+    acc[1] = acc[1] * fa + r[1] * fb;
+    acc[2] = acc[2] * fa + r[2] * fb;
+    acc[3] = acc[3] * fa * fa + r[3] * fb * fb;
+    acc[4] += r[4];
+    acc[5] += r[5];
+    acc[6] += r[6];
+    acc[7] = 0.0;
+}
+
+void empty_rows(double* rows, int64_t n_samples)
+{
+    for (int64_t j = 0; j < n_samples; ++j) {
+        double* r = rows + 8 * j;
+        r[0] = -INFINITY;
+        for (int k = 1; k < 8; ++k) r[k] = 0.0;
+    }
+}
+
+// The scalar statistic of an estimator: WINDOW the window energy, FIT lambda1 = e_ref - b,
+// FD the energy of the last sampling interval, MIXED the mixed estimate at the last row.
+int statistic(const double* rows, int64_t n_samples, double dt_sample, double e_ref, int32_t method,
+              const double* fit_w, double* tmp, double* out)
+{
+    const int rc = he_fk_energy(rows, n_samples, dt_sample, e_ref, method, fit_w, tmp, nullptr);
+    if (rc) return rc;
+    *out = (method == HE_FK_E_FD) ? tmp[n_samples - 2] : (method == HE_FK_E_MIXED) ? tmp[n_samples - 1] : tmp[0];
+    return HE_FK_OK;
+}
+
+}  // namespace
+
+extern "C" int he_fk_energy_blocks(const double* partials, int64_t n_parts, int64_t n_samples, int32_t n_groups,
+                                   double dt_sample, double e_ref, int32_t method, const double* fit_w,
+                                   double* est_out)
+{
+    if (!partials || !est_out || n_parts < 2 || n_samples < 1 || n_groups < 2) return HE_FK_EINVAL;
+    if (method < HE_FK_E_FD || method > HE_FK_E_MIXED) return HE_FK_EINVAL;
+    const int64_t G = n_groups < n_parts ? n_groups : n_parts;
+    // group g holds blocks [g q + min(g, r), (g + 1) q + min(g + 1, r)), q = n_parts / G, r = n_parts % G
+    const int64_t q = n_parts / G, rem = n_parts % G;
+    double* grows = new (std::nothrow) double[(size_t)(G + 2) * (size_t)n_samples * 8 + (size_t)n_samples + G];
+    if (!grows) return HE_FK_EINVAL;
+    double* all = grows + (size_t)G * n_samples * 8;
+    double* rest = all + (size_t)n_samples * 8;
+    double* tmp = rest + (size_t)n_samples * 8;  // [n_samples]: the estimator's output
+    double* reps = tmp + n_samples;              // [G]: the delete-one-group replicas
+    int64_t b = 0;
+    for (int64_t g = 0; g < G; ++g) {
+        double* gr = grows + (size_t)g * n_samples * 8;
+        empty_rows(gr, n_samples);
+        const int64_t end = (g + 1) * q + ((g + 1) < rem ? (g + 1) : rem);
+        for (; b < end; ++b)
+            for (int64_t j = 0; j < n_samples; ++j) merge_row(gr + 8 * j, partials + ((size_t)b * n_samples + j) * 8);
+    }
+    empty_rows(all, n_samples);
+    for (int64_t g = 0; g < G; ++g)
+        for (int64_t j = 0; j < n_samples; ++j) merge_row(all + 8 * j, grows + ((size_t)g * n_samples + j) * 8);
+    int rc = statistic(all, n_samples, dt_sample, e_ref, method, fit_w, tmp, &est_out[0]);
+    // delete-one-group replicas: their mean, then the jackknife variance (G - 1)/G sum (x_g - mean)^2
+    double sum = 0.0;
+    for (int64_t g = 0; g < G && !rc; ++g) {
+        empty_rows(rest, n_samples);
+        for (int64_t h = 0; h < G; ++h)
+            if (h != g)
+                for (int64_t j = 0; j < n_samples; ++j) merge_row(rest + 8 * j, grows + ((size_t)h * n_samples + j) * 8);
+        rc = statistic(rest, n_samples, dt_sample, e_ref, method, fit_w, tmp, &reps[g]);
+        sum += reps[g];
+    }
+    if (!rc) {
+        const double mean = sum / (double)G;
+        double ss = 0.0;
+        for (int64_t g = 0; g < G; ++g) ss += (reps[g] - mean) * (reps[g] - mean);
+        est_out[1] = sqrt((double)(G - 1) / (double)G * ss);
+    }
+    delete[] grows;
+    return rc;
 }

@@ -54,15 +54,15 @@ def _run(cfg, seed, samples_every=None, keep_L=False):
     wall = time.perf_counter() - t0
     dts = c["dt"] * se
     e_win = float(he_fk_energy(host, dts, c["e_ref"], "window")[0][0])
-    e_fd = he_fk_energy(host, dts, c["e_ref"], "fd")[0]
+    e_fd, aux, _ = he_fk_energy(host, dts, c["e_ref"], "fd")
     e_mix = he_fk_energy(host, dts, c["e_ref"], "mixed")[0]
     _, jk = jackknife(e.block_rows(c["n_steps"], se).cpu().numpy(), dts, c["e_ref"], "window")
     out = {"seed": seed, "E_window": e_win, "E_window_jackknife": jk, "E_fd_last": float(e_fd[-1]),
            "E_mixed_0": float(e_mix[0]), "E_mixed_last": float(e_mix[-1]), "alive_fraction": float(host[-1, 4] / host[-1, 6]),
            "nonfinite": int(host[:, 5].max()), "wall_s": wall, "propagate_s": ev0.elapsed_time(ev1) / 1e3,
-           "ess_last": float(host[-1, 1] ** 2 / host[-1, 3])}
+           "ess_last": float(aux[-1, 1])}
     if keep_L:
-        out["L"] = (host[:, 0] + np.log(host[:, 1]) - np.log(host[:, 6])).tolist()
+        out["L"] = aux[:, 0].tolist()
         out["alive"] = (host[:, 4] / host[:, 6]).tolist()
     del e
     torch.cuda.empty_cache()
@@ -174,8 +174,9 @@ def c4(seeds=32, first_step=0.02):
             _, _, el = e.state()
             sig.append(float(el.std()))
             h = e.propagate(0, c["n_steps"], c["sample_every"]).cpu().numpy()
-            E.append(float(he_fk_energy(h, c["dt"] * c["sample_every"], c["e_ref"], "fd")[0][-1]))
-            ess.append(float(h[-1, 1] ** 2 / h[-1, 3] / h[-1, 6]))
+            e_fd, aux, _ = he_fk_energy(h, c["dt"] * c["sample_every"], c["e_ref"], "fd")
+            E.append(float(e_fd[-1]))
+            ess.append(float(aux[-1, 1] / h[-1, 6]))
             del e
         m, se = _mean_se(E)
         return {"theta": [float(theta[0]), float(theta[1])], "E_T_mean": m, "E_T_se": se,

@@ -124,6 +124,7 @@ def test_energy_estimators_match_oracle(n):
     assert np.abs(out - est.e_fd(s, dts, e_ref)).max() < 1e-12
     assert np.abs(aux[:, 0] - est.log_mean_weight(s)).max() < 1e-14
     assert np.abs(aux[:, 1] - est.ess(s)).max() < 1e-9
+    assert np.abs(aux[:, 2] - est.log_mean_square_weight(s)).max() < 1e-14
     out, _, _ = api.he_fk_energy(s, dts, e_ref, "window")
     assert abs(out[0] - est.e_window(s, dts, e_ref)) < 1e-10
     out, _, _ = api.he_fk_energy(s, dts, e_ref, "fit")
@@ -135,6 +136,63 @@ def test_energy_estimators_match_oracle(n):
     assert abs(out[0] - Ef) < 1e-10
     out, _, _ = api.he_fk_energy(s, dts, e_ref, "mixed")
     assert np.abs(out - est.e_mixed(s)).max() < 1e-14
+
+
+@pytest.fixture(scope="module")
+def walker_weights():
+    # per-walker ln w and E_L at the sample times of an oracle run (4096 walkers of the triplet
+    # trial, node absorption included), and the walkers of block 0 absorbed from sample 5 on, so
+    # that a whole block has no live walker at the later rows
+    cfg = W.get("he_2tripS_4m", precision="fp64", dt=0.01)
+    r = oracle.run(cfg, np.arange(4096), 200, 10)
+    ell = r["ell"].copy()
+    ell[:64, 5:] = -np.inf
+    return cfg, ell, r["els"]
+
+
+@pytest.mark.parametrize("method", ["window", "fit", "fd", "mixed"])
+@pytest.mark.parametrize("n_groups", [2, 5, 32, 64])
+def test_block_jackknife_matches_a_direct_jackknife(walker_weights, method, n_groups):
+    # the library's grouping, merge of partial rows and replicas against a jackknife written
+    # here from the walkers themselves: each group's and each replica's rows are recomputed
+    # from the walkers they hold (oracle.tuples), with the oracle's estimators
+    cfg, ell, els = walker_weights
+    block = 64                                  # 64 blocks of 64 walkers
+    G = ell.shape[0] // block
+    parts = np.stack([oracle.tuples(ell[b * block:(b + 1) * block], els[b * block:(b + 1) * block])
+                      for b in range(G)])
+    dts, e_ref = 10 * cfg["dt"], cfg["e_ref"]
+
+    def stat(rows):
+        if method == "window":
+            return est.e_window(rows, dts, e_ref)
+        if method == "fit":
+            return est.e_fit(rows, dts, e_ref)[0]
+        if method == "fd":
+            return est.e_fd(rows, dts, e_ref)[-1]
+        return est.e_mixed(rows)[-1]
+
+    full, se = api.he_fk_energy_blocks(parts, dts, e_ref, method, n_groups)
+    assert abs(full - stat(oracle.tuples(ell, els))) < 1e-11
+    sizes = [len(a) for a in np.array_split(np.arange(G), n_groups)]   # larger groups first
+    edges = np.concatenate([[0], np.cumsum(sizes)]) * block
+    reps = []
+    for g in range(n_groups):
+        keep = np.ones(ell.shape[0], dtype=bool)
+        keep[edges[g]:edges[g + 1]] = False
+        reps.append(stat(oracle.tuples(ell[keep], els[keep])))
+    reps = np.array(reps)
+    se_direct = math.sqrt((n_groups - 1) / n_groups * np.sum((reps - reps.mean()) ** 2))
+    assert abs(se - se_direct) < 1e-9 * max(se_direct, 1e-6), (se, se_direct)
+
+
+def test_block_jackknife_argument_checks():
+    parts = np.zeros((1, 4, 8))
+    with pytest.raises(_lib.HeFkError):
+        api.he_fk_energy_blocks(parts, 0.1, 0.0, "window")
+    parts = np.zeros((4, 4, 8))
+    with pytest.raises(_lib.HeFkError):
+        api.he_fk_energy_blocks(parts, 0.1, 0.0, "window", n_groups=1)
 
 
 @pytest.mark.parametrize("name,tol,weighted", [("paper_table3.txt", 1e-6, False), ("paper_table4.txt", 1e-6, False),
