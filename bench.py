@@ -26,13 +26,15 @@ sys.path.insert(0, ROOT)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="he_2P_pz_16m")
     ap.add_argument("--precision", default=None, help="override the workload's precision")
     ap.add_argument("--noise", default=None)
     ap.add_argument("--contract", type=int, default=None)
-    ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 steps for the speedup (0: skip)")
+    ap.add_argument("--fp64-steps", type=int, default=4,
+                    help="timed FP64 steps on the first seeds of the mixed leg, for the speedup and the paired "
+                         "mixed - FP64 energy difference (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16384)
     ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
@@ -390,12 +392,16 @@ def main():
     achieved = slots * n * K / kern / 1e12
     peak = PEAK_SLOTS_PER_S / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
+            "frac_is": "VALU issue utilisation: formula-counted issue slots per second over 256 CU x 4 SIMD x "
+                       "16 lanes x 2.4 GHz (the 78.6 TFLOP/s FMA rate / 2)",
             "traffic": committed_traffic(cfg), "kernel": "propagate_kernel", "slots_per_walker_step": slots,
             "transcendentals_per_walker_step": transcendentals_per_walker_step(cfg), "kernel_ms": kern * 1e3}
     fl = fp32_flops_per_walker_step(cfg)
     if fl:
+        roof["fp32_flops_per_walker_step"] = fl
         roof["fp32_tflops"] = fl * n * K / kern / 1e12
-        roof["fp32_flop_frac_of_157.3"] = roof["fp32_tflops"] / 157.3
+        roof["fp32_flop_frac_of_78.6_unpacked"] = roof["fp32_tflops"] / 78.6
+        roof["fp32_flop_frac_of_157.3_packed"] = roof["fp32_tflops"] / 157.3
 
     out = {
         "metric": "He walker-steps/s/GPU; mixed FP32 vs FP64 time-to-1e-5 Ha energy error",
@@ -403,10 +409,12 @@ def main():
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if cfg["precision"] == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": cfg["name"], "trial": cfg["trial"], "sym": cfg.get("sym", 1),
-                   "n_walkers": n, "n_steps": K, "dt": cfg["dt"], "T": K * cfg["dt"],
+                   "theta": cfg["theta"], "n_walkers": n, "n_steps": K, "dt": cfg["dt"], "T": K * cfg["dt"],
                    "sample_every": cfg["sample_every"], "precision": cfg["precision"],
                    "noise": cfg["noise"], "contract": cfg["contract"], "quad": cfg["quad"],
-                   "n_metropolis": cfg["n_metropolis"], "seeds": seeds},
+                   "drift_limit": cfg.get("drift_limit", 0.0), "plain": bool(cfg.get("plain", False)),
+                   "bridge": bool(cfg.get("bridge", False)), "n_metropolis": cfg["n_metropolis"],
+                   "seeds": seeds},
         "propagate_walker_steps_per_s": n * K / kern,
         "roofline": roof,
         "energy": {"E_window": main_leg["energies"], "jackknife_se": main_leg["errs"]},
@@ -414,7 +422,8 @@ def main():
 
     if args.fp64_steps > 0 and cfg["precision"] == "mixed":
         c64 = dict(cfg, precision="fp64")
-        leg = run_leg(c64, args.fp64_steps, 0, seeds[:args.fp64_steps])
+        n64 = min(args.fp64_steps, args.steps)
+        leg = run_leg(c64, n64, 0, seeds[:n64])
         w64 = sum(leg["walls"]) / len(leg["walls"])
         k64 = sum(leg["kern"]) / len(leg["kern"])
         out["fp64"] = {"value": n * K / w64, "ms_per_step": w64 * 1e3, "propagate_walker_steps_per_s": n * K / k64,
@@ -425,6 +434,7 @@ def main():
         m = len(leg["energies"])
         d = [main_leg["energies"][i] - leg["energies"][i] for i in range(m)]
         bias = sum(d) / m
+        bias_se = math.sqrt(sum((x - bias) ** 2 for x in d) / (m - 1) / m) if m > 1 else None
         eps = 1e-5
         s_mix = sum(main_leg["errs"]) / len(main_leg["errs"])
         s_64 = sum(leg["errs"]) / m
@@ -438,7 +448,8 @@ def main():
         t_64 = w64 * s_pool ** 2 / eps ** 2
         out["time_to_1e-5_Ha"] = {"mixed_s": t_mix, "fp64_s": t_64,
                                   "speedup": (t_64 / t_mix) if math.isfinite(t_mix) else 0.0,
-                                  "paired_bias_mixed_minus_fp64": bias, "sigma_pooled": s_pool,
+                                  "paired_bias_mixed_minus_fp64": bias, "paired_bias_se": bias_se,
+                                  "paired_seeds": m, "sigma_pooled": s_pool,
                                   "sigma_mixed_jackknife": s_mix, "sigma_fp64_jackknife": s_64,
                                   "note": "statistical error only (the time-step bias is common to both "
                                           "precisions); one pooled jackknife error for both, as the paired "

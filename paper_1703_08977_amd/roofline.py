@@ -173,13 +173,81 @@ def transcendentals_per_walker_step(cfg: dict) -> float:
     return float(count(cfg).trans)
 
 
+# binary32 floating-point operations of the step, term by term from the formulas the step
+# evaluates (the kernels' per-walker code).  Convention: add, sub, mul, div 1; fused
+# multiply-add 2; each hardware transcendental (sqrt, rsq, rcp, exp2, log2, sin, cos) 1;
+# negation, absolute value, copysign, compares, selects and conversions 0; products of
+# trial parameters alone are uniform over the launch and do not count, nor does a parameter
+# times the member of the pair (t1, t2) = (1, e^{-|d|}) or (e^{-|d|}, 1) that is exactly 1
+# (counted at a point with r1 < r2).  Binary64 work (ln w) is not included.
+FP32_NOISE = {
+    # per pair: the two uniforms, log2 u1, its product with the radius scale, sqrt, sin, cos
+    "c2": 6 * 2 + 3 * (1 + 1 + 1 + 2),  # 21-bit fields: (f + 1/2) 2^-21 as one fused multiply-add each
+    "c1": 6 * 1 + 3 * (1 + 1 + 1 + 2),  # 23-bit fields: the float 1.m minus (1 - 2^-24)
+    "pm1": 0,                           # +-1 by selects; sqrt(dt) is a constant
+}
+FP32_EULER = 6 * 2 * 2  # Y + (dt f) b, then + r u: two fused multiply-adds per coordinate
+# D = R1 - R2 (3); per distance the squared norm (3 mul, 2 add), v_rsq and r = q (1/r) (7 each, 21);
+# the projections R1.D and R2.D (5 each)
+FP32_GEOMETRY = 3 + 3 * 7 + 2 * 5
+FP32_LIMITER = 12 + 6 + 1  # |b|^2 (6 mul, 6 add); f = 2 rcp(1 + sqrt(1 + 2 a dt |b|^2)) (6); dt f (1)
+FP32_NODE_TEST = 1         # the product of the orbital factor with the carried sign
+
+
+def _fp32_jastrow(cusp_zero: bool) -> int:
+    # 1/s = rcp(1 + beta r12) (3), 1/s^2 (1), u' = c/s^2 (1); the radial part
+    # [2 c beta ((1/s + 2) + beta r12) - c^2 / s^2] / s^2 (8: three for the inner sum, its product,
+    # c^2 times 1/s^2, the difference, times 1/s^2, and the sum with the cusp term), whose cusp
+    # term (ee - 2c)/r12 adds a product when ee != 2c
+    return 3 + 1 + 1 + 8 + (0 if cusp_zero else 1)
+
+
+def _fp32_trial(trial: str) -> int:
+    drift = 3 + 6 * 2  # w D once per component (3), then a fused multiply-add per coordinate
+    if trial == "expo":
+        # a_i = -A / r_i (2), drift with w = 0 (15), E_L = -A^2 + (A - Z)(1/r1 + 1/r2) + ee/r12 (5)
+        return 2 + drift + 5
+    if trial == "pade":
+        # a_i (2), w = u'/r12 (1), drift, (h1 - h2).h12 (4), E_L (7)
+        return 2 + 1 + drift + 4 + 7
+    # the pair: d = (A - a)(r1 - r2) (2)
+    if trial == "triplet":
+        # e^{-|d|} - 1 by the series to x^7 beside e^x - 1 (five fused multiply-adds 10, x^2 and the
+        # last one 3, e^x - 1 as a product, v_exp and a subtraction 3: 16), e = 1 + em (1), 1/D (1),
+        # g1, g2 (3 each), the two Laplacian brackets (4 each) times t1, t2 (1 each), their
+        # difference and 1/D (2), g_i/r_i and u'/r12 (3), drift, cross term (6), E_L (7)
+        return 2 + 16 + 1 + 1 + 6 + (4 + 1) * 2 + 2 + 3 + drift + 6 + 7
+    if trial == "triplet_r0":
+        # e^{-|d|} (2), q_i = r0 - r_i (2), D (3), 1/D (1), u_i = 1 + A q_i (4), g1, g2 (5 each), the
+        # two Laplacian brackets (10 each) times t1, t2 (1 each), their difference and 1/D (2),
+        # g_i/r_i and u'/r12 (3), drift, cross term (6), E_L (7)
+        return 2 + 2 + 2 + 3 + 1 + 4 + 10 + (10 + 1) * 2 + 2 + 3 + drift + 6 + 7
+    if trial == "pz_sum":
+        # e^{-|d|} (2), 1/(t1 + t2) (2), z1 + z2 and its reciprocal (2), g1, g2 (3 each), a_i = g_i/r_i
+        # (2), u'/r12 (1), drift, the z terms of the drift (2), the two Laplacian brackets (4 each)
+        # times t1, t2 (1 each), their sum and 1/S (2), the node-gradient term 2/Zs (a1 z1 + a2 z2)
+        # and its sum (6), cross term (4), E_L (7)
+        return 2 + 2 + 2 + 2 + 6 + 2 + 1 + drift + 2 + (4 + 1) * 2 + 2 + 6 + 4 + 7
+    # P_z: e^{-|d|} (2), sym t2 (1), P (3), 1/P (1), k1, k2 (5 each), a_i (2 each), s_i = t/P (2),
+    # u'/r12 (1), drift, the z terms of the drift (2), the two Laplacian brackets (4 each) times
+    # z2 t1 and t2 z1 (2 each), their sum and 1/P (2), cross term (7), E_L (7)
+    return 2 + 2 + 1 + 3 + 1 + 10 + 4 + 2 + 1 + drift + 2 + (4 + 2) * 2 + 2 + 7 + 7
+
+
 def fp32_flops_per_walker_step(cfg: dict) -> float:
-    """binary32 floating-point operations of one mixed step (fma = 2, transcendental = 1)."""
+    """binary32 floating-point operations of one mixed step (the convention above)."""
     if cfg.get("precision", "fp64") != "mixed":
         return 0.0
-    base = {"expo": 50, "pade": 85, "triplet": 125, "triplet_r0": 130, "pz": 140, "pz_sum": 130}[cfg["trial"]]
-    noise = 0 if cfg.get("noise", "gauss") == "pm1" else 3 * 6 + 6
-    return float(12 * 2 + base + noise)
+    trial = cfg["trial"]
+    noise = "pm1" if cfg.get("noise", "gauss") == "pm1" else ("c2" if int(cfg.get("contract", 1)) == 2 else "c1")
+    n = FP32_NOISE[noise] + FP32_EULER + FP32_GEOMETRY + _fp32_trial(trial)
+    if trial != "expo":
+        n += _fp32_jastrow(float(cfg.get("ee", 1)) == 2.0 * float(cfg["theta"][2]))
+    if trial in NODE_TRIALS:
+        n += FP32_NODE_TEST
+    if cfg.get("drift_limit", 0.0) > 0:
+        n += FP32_LIMITER
+    return float(n)
 
 
 def _vjp(c: _Count, f, trial: str):

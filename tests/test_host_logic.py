@@ -385,3 +385,47 @@ def test_bench_cases_cover_every_trial_family_and_both_precisions():
     # the variant kernels (plain walk, node bridge) are timed in both precisions
     assert any(pl or br for _, p, pl, br in seen if p == "mixed")
     assert any(pl or br for _, p, pl, br in seen if p == "fp64")
+
+
+_FLOPC = None
+
+
+def _flop_harness():
+    global _FLOPC
+    if _FLOPC is None:
+        import shutil
+        import subprocess
+        import tempfile
+        hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+        exe = os.path.join(tempfile.mkdtemp(prefix="hefk_flops_"), "flop_count_host_check")
+        subprocess.check_call([hipcc, "-O1", "-std=c++17", "--offload-arch=gfx950", "-I",
+                               os.path.join(ROOT, "paper_1703_08977_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
+                               "-o", exe, os.path.join(ROOT, "tests", "flop_count_host_check.cpp")],
+                              stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+        _FLOPC = exe
+    return _FLOPC
+
+
+@pytest.mark.parametrize("name,over", [
+    ("he_2P_pz_16m", {}),                                         # the benchmark step
+    ("he_2P_pz_16m", dict(drift_limit=0.0, sym=-1, theta=[2.0, 0.3, 0.25, 0.5])),
+    ("he_2P_pz_16m", dict(noise="pm1")),
+    ("he_2tripS_4m", {}), ("he_2tripS_4m", dict(contract=1)),
+    ("he_1s_pade_1m", {}), ("he_1s_pade_1m", dict(contract=2)),
+    ("he_1s_expo_4k", dict(contract=2)),
+    ("he_2tripS_fn5_1m", {}), ("he_2tripS_fn5_1m", dict(noise="gauss", contract=2)),
+    ("he_2P_fn7_1m", {}), ("he_2P_fn7_1m", dict(noise="gauss", contract=2, drift_limit=1.0)),
+])
+def test_fp32_flop_count_of_the_step_matches_the_counted_host_build(name, over):
+    # the term-by-term binary32 FLOP count of the roofline module against the same step's code
+    # run on the host on a counting binary32 type
+    import subprocess
+    from paper_1703_08977_amd import roofline
+    cfg = W.get(name, **dict(over, precision="mixed"))
+    noise = 2 if cfg.get("noise", "gauss") == "pm1" else (1 if cfg.get("contract", 1) == 2 else 0)
+    line = "%d %d %d %d %d %r\n" % (oracle.TRIALS[cfg["trial"]], cfg.get("sym", 1), noise, cfg.get("ee", 1),
+                                    1 if cfg.get("drift_limit", 0.0) > 0 else 0, float(cfg["theta"][2]))
+    out = subprocess.run([_flop_harness()], input=line, capture_output=True, text=True, check=True).stdout.split()
+    flops, trans = int(out[0]), int(out[1])
+    assert roofline.fp32_flops_per_walker_step(cfg) == flops
+    assert roofline.transcendentals_per_walker_step(cfg) == trans
