@@ -21,9 +21,10 @@
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
  *     null stream); outputs are valid after that stream synchronises.
  *   - Return 0 on success or a negative HE_FK_E* code; nothing is enqueued
- *     when an argument check fails.  No exception crosses the ABI.  The
- *     library holds no mutable global state: calls on distinct buffers may
- *     run concurrently from different threads.
+ *     when an argument check fails.  No exception crosses the ABI.  Apart from
+ *     the static scratch of he_fk_propagate_noalloc, the library holds no
+ *     mutable global state: calls on distinct buffers may run concurrently
+ *     from different threads.
  */
 #ifndef HE_FK_H
 #define HE_FK_H
@@ -204,6 +205,26 @@ size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, i
 int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,
                     int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every,
                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * he_fk_propagate_noalloc: he_fk_propagate for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as he_fk_propagate, bitwise,
+ * without the workspace: the per-block partial rows live in a static device array
+ * of HE_FK_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held from the first call on that
+ * GPU until the process ends.  The call allocates nothing (no hipMalloc / hipFree).
+ *   - The rows need he_fk_propagate_workspace_bytes(p, n_steps, sample_every) bytes
+ *     (64 bytes per block and sample row; a grid has at most one block per resident
+ *     slot, so 128 sample rows fit 2048 blocks); a call needing more than
+ *     HE_FK_NOALLOC_SCRATCH_BYTES returns HE_FK_ESCRATCH before launching anything.
+ *   - The array keeps the last call's partial rows.  Calls that overlap on one GPU
+ *     (two streams, two threads) share it and race: serialise them.
+ * Errors: as he_fk_propagate (EINVAL, ESCRATCH, EDEVICE).
+ */
+#define HE_FK_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int he_fk_propagate_noalloc(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,
+                            int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every,
+                            void* stream);
 
 /* ---- energy estimators (host only, pure) ---- */
 #define HE_FK_E_FD 0     /* E_out[n_samples-1]: e_ref - (L_j - L_{j-1}) / dt_sample            */

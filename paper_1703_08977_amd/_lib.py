@@ -32,8 +32,9 @@ GRAD_MOMENT2 = 2  # gL carries a second block of weights, on L2_s = ln <w^2>_s
 FLAG_PLAIN = 1   # plain Feynman-Kac walk: no drift, integrand V - e_ref
 FLAG_BRIDGE = 2  # node-touch (Brownian bridge) survival weight per step (node trials)
 
-EXPORTS = ["he_fk_init", "he_fk_propagate_workspace_bytes", "he_fk_propagate",
+EXPORTS = ["he_fk_init", "he_fk_propagate_workspace_bytes", "he_fk_propagate", "he_fk_propagate_noalloc",
            "he_fk_energy", "he_fk_energy_blocks", "he_fk_grad_scratch_bytes", "he_fk_grad", "he_fk_strerror"]
+NOALLOC_SCRATCH_BYTES = 16 << 20  # HE_FK_NOALLOC_SCRATCH_BYTES
 
 
 class HeFkParams(ctypes.Structure):
@@ -78,6 +79,8 @@ def lib():
         L.he_fk_propagate_workspace_bytes.restype = ctypes.c_size_t
         L.he_fk_propagate.argtypes = [pp, wp, i64, i64, i32, vp, vp, i32, vp, ctypes.c_size_t, vp]
         L.he_fk_propagate.restype = ctypes.c_int
+        L.he_fk_propagate_noalloc.argtypes = [pp, wp, i64, i64, i32, vp, vp, i32, vp]
+        L.he_fk_propagate_noalloc.restype = ctypes.c_int
         L.he_fk_energy.argtypes = [dp, i64, ctypes.c_double, ctypes.c_double, i32, dp, dp, dp]
         L.he_fk_energy.restype = ctypes.c_int
         L.he_fk_energy_blocks.argtypes = [dp, i64, i64, i32, ctypes.c_double, ctypes.c_double, i32, dp, dp]

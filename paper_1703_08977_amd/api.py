@@ -71,6 +71,13 @@ def he_fk_propagate(p, w, step0, n_steps, sample_every, samples, ckpt, ckpt_ever
     return check(rc, "he_fk_propagate")
 
 
+def he_fk_propagate_noalloc(p, w, step0, n_steps, sample_every, samples, ckpt, ckpt_every, stream=None) -> int:
+    rc = lib().he_fk_propagate_noalloc(ctypes.byref(p), ctypes.byref(w), int(step0), int(n_steps),
+                                       int(sample_every), ctypes.c_void_p(samples), ctypes.c_void_p(ckpt or 0),
+                                       int(ckpt_every), _stream(stream))
+    return check(rc, "he_fk_propagate_noalloc")
+
+
 def he_fk_energy(samples: np.ndarray, dt_sample: float, e_ref: float, method: str, fit_w=None, raise_on_error=True):
     """Host estimator; returns (E array, aux [n,3] = (L, ESS, L2), status code)."""
     s = np.ascontiguousarray(samples, dtype=np.float64)

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "he_fk.h"
 #include "hefk_device.hpp"
@@ -378,6 +379,73 @@ static int check_steps(int64_t step0, int64_t n_steps, int32_t sample_every)
     return HE_FK_OK;
 }
 
+// Argument checks, then the propagate kernel and the merge of its per-block partial rows,
+// which go to `workspace` (at least `workspace_bytes` bytes of device memory).
+static int propagate_launch(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,
+                            int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every,
+                            void* workspace, size_t workspace_bytes, void* stream)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    rc = check_steps(step0, n_steps, sample_every);
+    if (rc) return rc;
+    if (!w || !w->x || !w->lnw || !w->el || !samples || !workspace) return HE_FK_EINVAL;
+    if (ckpt) {
+        if (p->precision != HE_FK_FP64 || ckpt_every < 1 || n_steps % ckpt_every != 0) return HE_FK_EINVAL;
+    }
+    int64_t g = 0;
+    rc = propagate_grid(p, &g);
+    if (rc) return rc;
+    const int64_t n_samples = n_steps / sample_every + 1;
+    const size_t need = (size_t)g * (size_t)n_samples * 8 * sizeof(double);
+    if (workspace_bytes < need) return HE_FK_ESCRATCH;
+    KArgs a = make_args(p);
+    a.x = w->x;
+    a.lnw = w->lnw;
+    a.el = w->el;
+    a.step0 = (int32_t)step0;
+    a.n_steps = (int32_t)n_steps;
+    a.sample_every = sample_every;
+    a.n_samples = (int32_t)n_samples;
+    a.ckpt_every = ckpt ? ckpt_every : 0;
+    a.ckpt = ckpt;
+    a.partials = (double*)workspace;
+    hipLaunchKernelGGL(propagate_fn(p), dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a);
+    if (hipGetLastError() != hipSuccess) return HE_FK_EDEVICE;
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)n_samples), dim3(kBlock), 0, (hipStream_t)stream,
+                       (const double*)workspace, (int)g, (int)n_samples, samples);
+    return hipGetLastError() == hipSuccess ? HE_FK_OK : HE_FK_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of he_fk_propagate_noalloc: the per-block partial rows live in this
+// static device array (one copy per GPU, held until the process ends).  Every
+// block writes its rows before it reads them, so nothing needs clearing.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in symbol): its device address is looked up once per device, with that
+// device current, and kept here.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) double scratch[HE_FK_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int static_scratch(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HE_FK_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return HE_FK_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HE_FK_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HE_FK_OK;
+}
+
 }  // namespace hefk
 
 using namespace hefk;
@@ -412,38 +480,24 @@ int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0
                     int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every, void* workspace,
                     size_t workspace_bytes, void* stream)
 {
+    if (!workspace) return HE_FK_EINVAL;
+    return propagate_launch(p, w, step0, n_steps, sample_every, samples, ckpt, ckpt_every, workspace,
+                            workspace_bytes, stream);
+}
+
+int he_fk_propagate_noalloc(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,
+                            int32_t sample_every, double* samples, double* ckpt, int32_t ckpt_every, void* stream)
+{
     int rc = check_params(p);
     if (rc) return rc;
     rc = check_steps(step0, n_steps, sample_every);
     if (rc) return rc;
-    if (!w || !w->x || !w->lnw || !w->el || !samples || !workspace) return HE_FK_EINVAL;
-    if (ckpt) {
-        if (p->precision != HE_FK_FP64 || ckpt_every < 1 || n_steps % ckpt_every != 0) return HE_FK_EINVAL;
-    }
-    int64_t g = 0;
-    rc = propagate_grid(p, &g);
+    void* ws = nullptr;
+    rc = static_scratch(&ws);
     if (rc) return rc;
-    const int64_t n_samples = n_steps / sample_every + 1;
-    const size_t need = (size_t)g * (size_t)n_samples * 8 * sizeof(double);
-    if (workspace_bytes < need) return HE_FK_ESCRATCH;
-    KArgs a = make_args(p);
-    a.x = w->x;
-    a.lnw = w->lnw;
-    a.el = w->el;
-    a.step0 = (int32_t)step0;
-    a.n_steps = (int32_t)n_steps;
-    a.sample_every = sample_every;
-    a.n_samples = (int32_t)n_samples;
-    a.ckpt_every = ckpt ? ckpt_every : 0;
-    a.ckpt = ckpt;
-    a.partials = (double*)workspace;
-    hipLaunchKernelGGL(propagate_fn(p), dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a);
-    if (hipGetLastError() != hipSuccess) return HE_FK_EDEVICE;
-    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)n_samples), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const double*)workspace, (int)g, (int)n_samples, samples);
-    return hipGetLastError() == hipSuccess ? HE_FK_OK : HE_FK_EDEVICE;
+    return propagate_launch(p, w, step0, n_steps, sample_every, samples, ckpt, ckpt_every, ws,
+                            (size_t)HE_FK_NOALLOC_SCRATCH_BYTES, stream);
 }
-
 const char* he_fk_strerror(int code)
 {
     switch (code) {

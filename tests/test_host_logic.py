@@ -69,6 +69,8 @@ def test_invalid_params_rejected_before_any_launch():
     for p in _bad_params():
         assert _lib.lib().he_fk_init(ctypes.byref(p), ctypes.byref(w), None) == _lib.HE_FK_EINVAL
         assert _lib.lib().he_fk_propagate_workspace_bytes(ctypes.byref(p), 10, 5) == 0
+        assert _lib.lib().he_fk_propagate_noalloc(ctypes.byref(p), ctypes.byref(w), 0, 10, 5, ctypes.c_void_p(1),
+                                                  None, 0, None) == _lib.HE_FK_EINVAL
     p = api.make_params(W.get("he_1s_expo_4k"))
     assert _lib.lib().he_fk_init(ctypes.byref(p), None, None) == _lib.HE_FK_EINVAL
     z = _lib.HeFkWalkers(0, 0, 0)
@@ -77,6 +79,9 @@ def test_invalid_params_rejected_before_any_launch():
     for (s0, ns, se) in ((0, 10, 3), (-1, 10, 5), (0, -5, 5), (0, 10, 0), (2**31 - 5, 10, 5)):
         rc = _lib.lib().he_fk_propagate(ctypes.byref(p), ctypes.byref(w), s0, ns, se, ctypes.c_void_p(1),
                                         None, 0, ctypes.c_void_p(1), ctypes.c_size_t(1 << 30), None)
+        assert rc == _lib.HE_FK_EINVAL
+        rc = _lib.lib().he_fk_propagate_noalloc(ctypes.byref(p), ctypes.byref(w), s0, ns, se, ctypes.c_void_p(1),
+                                                None, 0, None)
         assert rc == _lib.HE_FK_EINVAL
 
 
