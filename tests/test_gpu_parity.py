@@ -110,6 +110,7 @@ CASES = [
     ("hydrogen", dict()),
     ("he_1s_pade_1m", dict(dt=0.01, drift_limit=0.5, contract=2)),
     ("he_2tripS_fn3_1m", dict(precision="fp64")),
+    ("he_2tripS_fn3_1m", dict(precision="fp64", drift_limit=1.0)),   # +-1 walk, right sum, limiter
     ("he_2tripS_fn4_1m", dict(precision="fp64")),
     ("he_2P_fn7_1m", dict(precision="fp64")),
     ("he_2P_fn7_1m", dict(precision="fp64", noise="gauss", quad="trapezoid", dt=0.002, bridge=True)),

@@ -259,6 +259,7 @@ HOST_CASES = [
     ("he_2P_pz_16m", {"dt": 0.005, "sym": -1, "theta": [2.0, 0.3, 0.25, 0.5], "noise": "pm1"}),
     ("hydrogen", {}),
     ("he_2tripS_fn3_1m", {"precision": "fp64"}),
+    ("he_2tripS_fn3_1m", {"precision": "fp64", "drift_limit": 1.0}),
     ("he_2tripS_fn5_1m", {"precision": "fp64", "noise": "gauss", "contract": 2, "quad": "trapezoid"}),
     ("he_1s_pade_1m", {"plain": True}),
     ("he_2tripS_4m", {"dt": 0.005, "plain": True}),
