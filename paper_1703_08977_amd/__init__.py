@@ -5,6 +5,6 @@ package marshals arguments (``api``), holds the seeded workload definitions
 (``workloads``) and wraps the pathwise gradient in a torch.autograd.Function
 (``autograd``).
 """
-from .api import (Ensemble, he_fk_energy, he_fk_grad, he_fk_grad_scratch_bytes, he_fk_init,  # noqa: F401
+from .api import (Ensemble, he_fk_energy, he_fk_energy_blocks, he_fk_grad, he_fk_grad_scratch_bytes, he_fk_init,  # noqa: F401
                   he_fk_propagate, he_fk_propagate_noalloc, he_fk_propagate_workspace_bytes, make_params, run)
 from . import workloads  # noqa: F401

@@ -1,6 +1,6 @@
 """End-to-end runs of the five workloads on one GPU (energies, errors, timings).
 
-    python -m paper_1703_08977_amd.studies {c1,c2,c3,c4,c5,all} [--seeds N] [--out file.json]
+    python -m paper_1703_08977_amd.studies {c1,...,paper_limited,all} [--seeds N] [--out file.json]
 
 c1  1^1S, exp(-alpha(r1+r2)), alpha = 27/16, 4096 walkers: E_fd(t), E_mixed(0) (variational).
 c2  1^1S, Pade-Jastrow, 2^20 walkers, T = 5, dt in {0.002, 0.001, 0.0005}: window energy
@@ -22,6 +22,11 @@ plain  the plain Feynman-Kac walk of eqs. (2)-(3) against the generalized one on
     seeds: He ground state (Pade-Jastrow start) and two hydrogen atoms (exact energy -1).
 bridge the node-touch (Brownian bridge) weight: the exact 1s2s triplet without 1/r12
     (E = -5/2, exact node) for both walks, and the triplet workload, per dt.
+triplet_limit  the triplet trial projected to T = 72 at dt in {0.004, ..., 0.00025} (mixed; binary64
+    at dt = 0.001), 2^22 walkers: window energies, the plateau energy over [40, 72], and its
+    extrapolation E0 + a sqrt(dt) + b dt.
+paper_limited  the paper's setting for trial functions 3 (dt = 1/900, 1/1800, 1/3600) and 4
+    (dt = 1/900) with the drift and integrand limiting on: lambda1 per dt and at dt -> 0.
 Exact non-relativistic energies (the "Var" row of Table 6) are reported beside.
 """
 from __future__ import annotations
@@ -294,6 +299,118 @@ def longt(seeds=8):
     return out
 
 
+def _plateau_fit(rows, key="E_plateau"):
+    """Weighted least squares of E(dt) = E0 + a sqrt(dt) + b dt over the rows; (E0, se, a, b)."""
+    x = np.array([r["dt"] for r in rows])
+    y = np.array([r[key] for r in rows])
+    w = 1.0 / np.maximum(np.array([r[key + "_se"] for r in rows]), 1e-12) ** 2
+    A = np.stack([np.ones_like(x), np.sqrt(x), x], axis=1)
+    cov = np.linalg.inv(A.T @ (A * w[:, None]))
+    coef = cov @ (A.T @ (w * y))
+    chi2 = float(np.sum(w * (A @ coef - y) ** 2))
+    return float(coef[0]), float(math.sqrt(cov[0, 0])), float(coef[1]), float(coef[2]), chi2
+
+
+def triplet_limit(seeds=8, T=72.0, dts=(0.004, 0.002, 0.001, 0.0005, 0.00025), fp64_dt=0.001, t_plateau=40.0):
+    """The 2^3S energy of the triplet trial (exact node r1 = r2) in the limit of long projection and
+    small time step, 2^22 walkers, L(t) sampled every 0.5.  Per dt: the window energies over
+    [T'/2, T'], and the plateau energy e_ref - slope of L over [t_plateau, T], where the projection
+    onto the lowest state of the nodal pocket is complete (the energy over successive 8-unit
+    intervals is flat from t ~ 40 on).  The exact node is never reached by the continuous drifted
+    process, so every absorption is a discretisation event, at a rate ~ sqrt(dt); the plateau
+    energies are therefore extrapolated with E0 + a sqrt(dt) + b dt.  Mixed precision, and binary64
+    at one dt on the same seeds."""
+    from . import workloads as W
+    out = {"exact": EXACT["3S"], "T": T, "t_plateau": t_plateau, "seeds": seeds, "per_dt": []}
+    legs = [(dt, "mixed") for dt in dts] + ([(fp64_dt, "fp64")] if fp64_dt else [])
+    for dt, prec in legs:
+        se = int(round(0.5 / dt))
+        cfg = W.get("he_2tripS_4m", precision=prec, dt=dt, n_steps=int(round(T / dt)), sample_every=se)
+        runs = [_run(cfg, s_, keep_L=True) for s_ in range(seeds)]
+        dts_ = dt * se
+        wins = {}
+        for tw in (16, 24, 32, 48, 64, 80, 96):
+            if tw > T:
+                continue
+            vals = []
+            for r in runs:
+                L = np.asarray(r["L"])
+                i0, i1 = int(round(tw / 2 / dts_)), int(round(tw / dts_))
+                t = np.arange(i0, i1 + 1) * dts_
+                vals.append(cfg["e_ref"] - np.polyfit(t, L[i0:i1 + 1], 1)[0])
+            m, s_ = _mean_se(vals)
+            wins[str(tw)] = {"E": m, "se": s_, "minus_exact": m - EXACT["3S"]}
+        plat = []
+        for r in runs:
+            L = np.asarray(r["L"])
+            i0 = int(round(t_plateau / dts_))
+            t = np.arange(i0, len(L)) * dts_
+            plat.append(cfg["e_ref"] - np.polyfit(t, L[i0:], 1)[0])
+        pm, ps = _mean_se(plat)
+        row = {"dt": dt, "precision": prec, "e_ref": cfg["e_ref"], "sample_dt": dts_, "windows": wins,
+               "E_plateau": pm, "E_plateau_se": ps, "E_plateau_minus_exact": pm - EXACT["3S"],
+               "alive_last": float(np.mean([r["alive_fraction"] for r in runs])),
+               "ess_last_fraction": float(np.mean([r["ess_last"] for r in runs])) / cfg["n_walkers"],
+               "wall_s": float(np.mean([r["wall_s"] for r in runs])),
+               "L_seeds": [r["L"] for r in runs]}
+        out["per_dt"].append(row)
+        print("# triplet_limit dt=%g %s: plateau [%g, %g] %.7f(%.0f) alive %.4f; " %
+              (dt, prec, t_plateau, T, pm, ps * 1e7, row["alive_last"]) +
+              " ".join("T%s %.6f(%.0f)" % (k, v["E"], v["se"] * 1e6) for k, v in wins.items()),
+              file=sys.stderr, flush=True)
+    mixed = [r for r in out["per_dt"] if r["precision"] == "mixed"]
+    if len(mixed) >= 4:
+        e0, e0s, a, b, chi2 = _plateau_fit(mixed)
+        out["fit_sqrt_dt"] = {"E0": e0, "E0_se": e0s, "a_sqrt_dt": a, "b_dt": b, "chi2": chi2,
+                              "dof": len(mixed) - 3, "E0_minus_exact": e0 - EXACT["3S"],
+                              "E0_minus_exact_over_se": (e0 - EXACT["3S"]) / e0s}
+        print("# triplet_limit E0 + a sqrt(dt) + b dt: E0 %.7f +- %.7f (%.1f sigma from exact), a %.4g, b %.4g, "
+              "chi2 %.2f / %d" % (e0, e0s, (e0 - EXACT["3S"]) / e0s, a, b, chi2, len(mixed) - 3),
+              file=sys.stderr, flush=True)
+    return out
+
+
+def paper_limited(seeds=8):
+    """The paper's 2^3S settings (+-1 walk, right end-point sum, the paper's fit over t = 8..48) with
+    the drift and integrand limiting on (a = 1, the reading of the paper's criterion that keeps
+    electrons off the nucleus and off each other): trial function 3 at dt = 1/900, 1/1800, 1/3600
+    and trial function 4 at dt = 1/900; lambda1 per dt and extrapolated linearly to dt = 0."""
+    from . import Ensemble, he_fk_energy
+    from . import workloads as W
+    out = {"exact": EXACT["3S"], "paper_lambda1_context": {"fn3": -2.17536239}}
+    for name, scales in (("he_2tripS_fn3_1m", (900, 1800, 3600)), ("he_2tripS_fn4_1m", (900,))):
+        rows = []
+        for n in scales:
+            cfg = W.get(name, dt=1.0 / n, n_steps=48 * n, sample_every=n, drift_limit=1.0)
+            t_fit = np.array(cfg["t_fit"], dtype=np.float64)
+            lam1, ess, nonfinite = [], [], 0
+            for seed in range(seeds):
+                c = dict(cfg, seed=seed)
+                e = Ensemble(c).init()
+                s = e.propagate(0, c["n_steps"], c["sample_every"]).cpu().numpy()
+                nonfinite += int(s[:, 5].max())
+                _, aux, _ = he_fk_energy(s, 1.0, c["e_ref"], "mixed")
+                lz = aux[t_fit.astype(int), 0]
+                A = np.stack([np.ones_like(t_fit), 1.0 / t_fit], axis=1)
+                b, _ = np.linalg.lstsq(A, lz / t_fit, rcond=None)[0]
+                lam1.append(c["e_ref"] - b)
+                ess.append(float(aux[-1, 1] / s[-1, 6]))
+                del e
+            m, se = _mean_se(lam1)
+            rows.append({"dt": 1.0 / n, "scale": n, "lambda1": m, "lambda1_se": se, "E_window": m,
+                         "E_window_se": se, "lambda1_minus_exact": m - EXACT["3S"],
+                         "ess_fraction_t48": float(np.mean(ess)), "nonfinite_rows": nonfinite})
+            print("# paper_limited %s dt=1/%d: lambda1 %.7f +- %.7f (ESS/N at t = 48: %.3g)" %
+                  (name, n, m, se, float(np.mean(ess))), file=sys.stderr, flush=True)
+        res = {"per_dt": rows}
+        if len(rows) > 1:
+            e0, e0s, slope = _dt0(rows)
+            res.update({"lambda1_dt0": e0, "lambda1_dt0_se": e0s, "dt_slope": slope,
+                        "lambda1_dt0_minus_exact": e0 - EXACT["3S"]})
+        out[name] = res
+    return out
+
+
 def plain(seeds=8):
     from . import workloads as W
     out = {}
@@ -369,12 +486,13 @@ def bridge(seeds=4):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "paper", "longt", "plain", "bridge", "all"])
+    ap.add_argument("which", choices=["c1", "c2", "c3", "c4", "c5", "paper", "longt", "plain", "bridge",
+                                      "triplet_limit", "paper_limited", "all"])
     ap.add_argument("--seeds", type=int, default=None)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     fns = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "paper": paper, "longt": longt, "plain": plain,
-           "bridge": bridge}
+           "bridge": bridge, "triplet_limit": triplet_limit, "paper_limited": paper_limited}
     todo = list(fns) if a.which == "all" else [a.which]
     res = {}
     for k in todo:
