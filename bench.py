@@ -369,7 +369,8 @@ def main():
         return
     import torch
     from paper_1703_08977_amd import workloads as W
-    from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, fp32_flops_per_walker_step, slots_per_walker_step,
+    from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, fp32_flops_per_walker_step,
+                                               instructions_per_walker_step, slots_per_walker_step,
                                                transcendentals_per_walker_step)
 
     over = {}
@@ -392,10 +393,12 @@ def main():
     achieved = slots * n * K / kern / 1e12
     peak = PEAK_SLOTS_PER_S / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-            "frac_is": "VALU issue utilisation: formula-counted issue slots per second over 256 CU x 4 SIMD x "
-                       "16 lanes x 2.4 GHz (the 78.6 TFLOP/s FMA rate / 2)",
+            "frac_is": "VALU main-pipe issue utilisation: formula-counted main-pipe slots per second over "
+                       "256 CU x 4 SIMD x 16 lanes x 2.4 GHz (the 78.6 TFLOP/s FMA rate / 2); the hardware "
+                       "transcendentals issue beside the main pipe and are counted apart",
             "traffic": committed_traffic(cfg), "kernel": "propagate_kernel", "slots_per_walker_step": slots,
-            "transcendentals_per_walker_step": transcendentals_per_walker_step(cfg), "kernel_ms": kern * 1e3}
+            "transcendentals_per_walker_step": transcendentals_per_walker_step(cfg),
+            "valu_instructions_per_walker_step": instructions_per_walker_step(cfg), "kernel_ms": kern * 1e3}
     fl = fp32_flops_per_walker_step(cfg)
     if fl:
         roof["fp32_flops_per_walker_step"] = fl

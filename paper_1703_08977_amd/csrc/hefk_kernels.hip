@@ -57,6 +57,7 @@ struct KArgs {
     int64_t n;
     int32_t n_metropolis;
     int32_t step0, n_steps, sample_every, n_samples, ckpt_every;
+    int32_t rows_in_lds;  // the block's partial rows accumulate in LDS, written to `partials` once
     void* x;
     double* lnw;
     void* el;
@@ -129,16 +130,30 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const KArgs a)
 // (chunk c = blockIdx.x + j * gridDim.x); each lane keeps its walker in
 // registers for all n_steps steps.  At every sampling time the block reduces
 // (max ln w, then S0, S1, S2 and counts) and merges the result into its own
-// partial row in the workspace.
+// partial row.  The rows accumulate in LDS when they fit (kRowsLdsBytes) and
+// go to the workspace once, at the end; otherwise they are merged in place in
+// the workspace, chunk after chunk.
 // ---------------------------------------------------------------------------
+#ifndef HEFK_ROWS_LDS_BYTES
+#define HEFK_ROWS_LDS_BYTES 16384  // 256 sample rows of 64 bytes per block (0: rows merged in the workspace)
+#endif
+constexpr int kRowsLdsBytes = HEFK_ROWS_LDS_BYTES;
 template <typename R>
-__device__ __forceinline__ void sample_row(const KArgs& a, double* part_row, bool first, bool valid,
-                                           const WalkerState<R>& w, double* red)
+__device__ __forceinline__ void sample_row(const KArgs& a, int row, double* rows_out, double* rows_lds, bool first,
+                                           bool valid, const WalkerState<R>& w, double* red)
 {
     Tuple t = block_tuple(valid, w.lnw, (double)w.el, red);
     if (threadIdx.x == 0) {
-        if (!first) t = merge_tuple(load_tuple(part_row), t);
-        store_tuple(part_row, t);
+        // two paths, so that each row access has a known address space (LDS or global)
+        if (a.rows_in_lds) {
+            double* r = rows_lds + (size_t)row * 8;
+            if (!first) t = merge_tuple(load_tuple(r), t);
+            store_tuple(r, t);
+        } else {
+            double* r = rows_out + (size_t)row * 8;
+            if (!first) t = merge_tuple(load_tuple(r), t);
+            store_tuple(r, t);
+        }
     }
 }
 
@@ -147,11 +162,12 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
     const KArgs a)
 {
     __shared__ double red[kRedSlots];
+    extern __shared__ double rows_lds[];  // [n_samples][8] when a.rows_in_lds
     const TrialParams<R>& tp = tparams<R>(a);
     const StepScale<R>& ss = sscale<R>(a);
     const int64_t n = a.n;
     const int64_t n_chunks = (n + kBlock - 1) / kBlock;
-    double* part = a.partials + (size_t)blockIdx.x * (size_t)a.n_samples * 8;
+    double* const rows_out = a.partials + (size_t)blockIdx.x * (size_t)a.n_samples * 8;
     R* x = (R*)a.x;
 
     for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
         w.lnw = a.lnw[ii];
         walker_reset<R, TRIAL, EXT>(tp, a.sc, ss, w);
 
-        sample_row<R>(a, part, first, valid, w, red);
+        sample_row<R>(a, 0, rows_out, rows_lds, first, valid, w, red);
         if (a.ckpt && valid) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) a.ckpt[(int64_t)k * n + i] = (double)w.y[k];
@@ -181,7 +197,7 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
             walker_step<R, TRIAL, EXT>(tp, a.sc, ss, inc, w);
             if (--until_sample == 0) {
                 until_sample = a.sample_every;
-                sample_row<R>(a, part + (size_t)row * 8, first, valid, w, red);
+                sample_row<R>(a, row, rows_out, rows_lds, first, valid, w, red);
                 ++row;
             }
             if (a.ckpt && --until_ckpt == 0) {
@@ -201,6 +217,10 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
             a.lnw[i] = w.lnw;
             ((R*)a.el)[i] = w.el;
         }
+    }
+    if (a.rows_in_lds) {
+        __syncthreads();  // thread 0's last merge into LDS is complete
+        for (int k = threadIdx.x; k < a.n_samples * 8; k += kBlock) rows_out[k] = rows_lds[k];
     }
 }
 
@@ -350,15 +370,22 @@ static KArgs make_args(const he_fk_params* p)
     return a;
 }
 
+// Dynamic LDS of a propagate launch: the block's partial rows when they fit.
+static size_t rows_lds_bytes(int64_t n_samples)
+{
+    const size_t b = (size_t)n_samples * 8 * sizeof(double);
+    return b <= (size_t)kRowsLdsBytes ? b : 0;
+}
+
 // Blocks of a propagate launch: every block resident at once, none without a chunk.
-static int propagate_grid(const he_fk_params* p, int64_t* out)
+static int propagate_grid(const he_fk_params* p, size_t lds_bytes, int64_t* out)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HE_FK_EDEVICE;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return HE_FK_EDEVICE;
     KernelFn fn = propagate_fn(p);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, lds_bytes) != hipSuccess)
         return HE_FK_EDEVICE;
     if (per_cu < 1) per_cu = 1;
     const int64_t n_chunks = (p->n_walkers + kBlock - 1) / kBlock;
@@ -393,10 +420,11 @@ static int propagate_launch(const he_fk_params* p, const he_fk_walkers* w, int64
     if (ckpt) {
         if (p->precision != HE_FK_FP64 || ckpt_every < 1 || n_steps % ckpt_every != 0) return HE_FK_EINVAL;
     }
-    int64_t g = 0;
-    rc = propagate_grid(p, &g);
-    if (rc) return rc;
     const int64_t n_samples = n_steps / sample_every + 1;
+    const size_t lds = rows_lds_bytes(n_samples);
+    int64_t g = 0;
+    rc = propagate_grid(p, lds, &g);
+    if (rc) return rc;
     const size_t need = (size_t)g * (size_t)n_samples * 8 * sizeof(double);
     if (workspace_bytes < need) return HE_FK_ESCRATCH;
     KArgs a = make_args(p);
@@ -410,7 +438,8 @@ static int propagate_launch(const he_fk_params* p, const he_fk_walkers* w, int64
     a.ckpt_every = ckpt ? ckpt_every : 0;
     a.ckpt = ckpt;
     a.partials = (double*)workspace;
-    hipLaunchKernelGGL(propagate_fn(p), dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a);
+    a.rows_in_lds = lds ? 1 : 0;
+    hipLaunchKernelGGL(propagate_fn(p), dim3((unsigned)g), dim3(kBlock), lds, (hipStream_t)stream, a);
     if (hipGetLastError() != hipSuccess) return HE_FK_EDEVICE;
     hipLaunchKernelGGL(merge_kernel, dim3((unsigned)n_samples), dim3(kBlock), 0, (hipStream_t)stream,
                        (const double*)workspace, (int)g, (int)n_samples, samples);
@@ -471,9 +500,10 @@ int he_fk_init(const he_fk_params* p, const he_fk_walkers* w, void* stream)
 size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, int32_t sample_every)
 {
     if (check_params(p) || check_steps(0, n_steps, sample_every)) return 0;
+    const int64_t n_samples = n_steps / sample_every + 1;
     int64_t g = 0;
-    if (propagate_grid(p, &g)) return 0;
-    return (size_t)g * (size_t)(n_steps / sample_every + 1) * 8 * sizeof(double);
+    if (propagate_grid(p, rows_lds_bytes(n_samples), &g)) return 0;
+    return (size_t)g * (size_t)n_samples * 8 * sizeof(double);
 }
 
 int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,

@@ -5,23 +5,23 @@ floating point; no contraction, no HBM traffic between sampling times), so
 its roofline is the vector-ALU issue rate.
 
 Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s,
-one VALU instruction slot per lane per clock (a wave64 instruction occupies a
-16-lane SIMD for 4 clocks).  This is the published 78.6 TFLOP/s binary32 (and
-binary64) FMA rate divided by 2 flops; the 157.3 TFLOP/s binary32 figure needs
-packed (v_pk_*) instructions, which this library does not use.
+one main-pipe VALU instruction slot per lane per clock (a wave64 instruction
+occupies a 16-lane SIMD for 4 clocks).  This is the published 78.6 TFLOP/s
+binary32 (and binary64) FMA rate divided by 2 flops; the 157.3 TFLOP/s
+binary32 figure needs packed (v_pk_*) instructions, which this library does
+not use.
 
-Work: every elementary operation of the step's formulas counts one slot --
-add, mul, fma, compare, select, convert, 32-bit integer op, 32x32->64
-multiply, three-input xor, and each binary32 hardware transcendental (v_sqrt,
-v_rsq, v_rcp, v_exp, v_log, v_sin, v_cos).  The transcendentals take VALU
-issue slots like the rest: the hardware counters count them among the VALU
-instructions, and over the mixed P_z step those instructions, transcendentals
-included, issue at 0.250 wave-instructions per SIMD-cycle -- one slot per
-cycle (a wave64 instruction holds a 16-lane SIMD for 4 clocks).  They are
-also reported apart.  Binary64 functions count their polynomial and
-range-reduction operations (the table F64 below), a binary64 select as two
-32-bit selects.  Counts follow the formulas term by term (they are not read
-back from the compiled code).
+Work: every elementary operation of the step's formulas counts one main-pipe
+slot -- add, mul, fma, compare, select, convert, 32-bit integer op,
+32x32->64 multiply, three-input xor.  The binary32 hardware transcendentals
+(v_sqrt, v_rsq, v_rcp, v_exp, v_log, v_sin, v_cos) are counted apart: they
+issue beside the main pipe.  The counters show it: the mixed P_z step's 205
+VALU instructions per wave-step (20 of them transcendental) issue at 0.262
+wave-instructions per SIMD-cycle at 2.38 GHz, above the 0.25 that one 4-cycle
+slot per instruction would allow, so the roofline is the main pipe's.
+Binary64 functions count their polynomial and range-reduction operations (the
+table F64 below), a binary64 select as two 32-bit selects.  Counts follow the
+formulas term by term (they are not read back from the compiled code).
 """
 from __future__ import annotations
 
@@ -163,7 +163,13 @@ def count(cfg: dict) -> _Count:
 
 
 def slots_per_walker_step(cfg: dict) -> float:
-    """VALU issue slots of one walker step: elementary operations and hardware transcendentals."""
+    """Main-pipe VALU issue slots of one walker step (the elementary operations; the hardware
+    transcendentals issue beside them and are counted by transcendentals_per_walker_step)."""
+    return float(count(cfg).main)
+
+
+def instructions_per_walker_step(cfg: dict) -> float:
+    """VALU instructions of one walker step, transcendentals included (what SQ_INSTS_VALU counts)."""
     c = count(cfg)
     return float(c.main + c.trans)
 
