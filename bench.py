@@ -37,6 +37,8 @@ def parse():
                          "mixed - FP64 energy difference (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16384)
+    ap.add_argument("--grad-walkers", type=int, default=0,
+                    help="grad mode: walkers of the gradient workload (0: its own 2^18)")
     ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle", "grad", "cases"],
                     help="copy: a plain 1 GiB device copy, three times (the reference reading of the HBM "
@@ -216,7 +218,7 @@ def oracle_timing(threads=0):
     print(json.dumps(out), flush=True)
 
 
-def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu):
+def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu, n_walkers=0):
     """Forward propagation with checkpoints, then the reverse sweep (he_fk_grad) of
     dE(T)/d(alpha, beta), E(T) = e_ref - (L(T) - L(T - ds)) / ds, score term included."""
     import numpy as np
@@ -225,7 +227,7 @@ def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu):
     from paper_1703_08977_amd import workloads as W
     from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, grad_slots_per_walker_step,
                                                grad_tape_bytes_per_walker_step)
-    cfg = W.get("he_1s_pade_grad_256k")
+    cfg = W.get("he_1s_pade_grad_256k", **({"n_walkers": n_walkers} if n_walkers else {}))
     n, K, se, ce = cfg["n_walkers"], cfg["n_steps"], cfg["sample_every"], cfg["ckpt_every"]
     ns = K // se + 1
     dts = cfg["dt"] * se
@@ -362,7 +364,7 @@ def main():
         oracle_timing(args.oracle_threads)
         return
     if args.mode == "grad":
-        grad_bench(args.steps, args.warmup, args.cpu_walkers, args.no_cpu_baseline)
+        grad_bench(args.steps, args.warmup, args.cpu_walkers, args.no_cpu_baseline, args.grad_walkers)
         return
     if args.mode == "cases":
         cases_bench(args.steps)
