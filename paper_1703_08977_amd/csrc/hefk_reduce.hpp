@@ -130,7 +130,11 @@ __device__ __forceinline__ double wave_max(double v)
 constexpr int kRedSlots = 4 * 8;  // 4 waves x 8 doubles
 
 // Block-wide tuple over the block's 256 lanes (blockDim.x == 256); the result
-// is valid in thread 0.  All threads of the block must call it.
+// is valid in thread 0.  All threads of the block must call it.  Two barriers
+// per call: every thread has read the maxima red[0..3] of a call before that
+// call's second barrier, and thread 0 has read its sums red[4..] before it
+// reaches the next call's first barrier, which the next sums are written after;
+// so consecutive calls need no barrier between them.
 __device__ __forceinline__ Tuple block_tuple(bool valid, double lnw, double el, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -138,7 +142,6 @@ __device__ __forceinline__ Tuple block_tuple(bool valid, double lnw, double el, 
     const bool alive = valid && !bad && lnw != -INFINITY;
     const double lv = alive ? lnw : -INFINITY;
     const double mw = wave_max(lv);
-    __syncthreads();  // the previous row's reads of red are done
     if (lane == 0) red[wave] = mw;
     __syncthreads();
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));

@@ -422,3 +422,32 @@ def test_run_helper_matches_the_oracle_estimators():
     assert np.abs(out["E_fd"] - est.e_fd(r["samples"], dts, cfg["e_ref"])).max() < 1e-9
     assert abs(out["E_window"] - est.e_window(r["samples"], dts, cfg["e_ref"])) < 1e-10
     assert np.isfinite(out["E_window_jackknife"]) and out["E_window_jackknife"] > 0
+
+
+# --------------------------------------------------------------------------
+# The two homes of a block's partial rows: LDS (up to 256 rows) and the
+# workspace (more rows).  The same walkers sampled every step (301 rows, the
+# workspace merge) and every other step (151 rows, LDS) give bitwise the same
+# rows at the common sampling times, and the same walkers.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,over", [("he_2P_pz_16m", {}), ("he_1s_pade_1m", dict(dt=0.002, precision="mixed")),
+                                       ("he_2tripS_4m", dict(precision="fp64"))], ids=["pz_mixed", "pade_mixed",
+                                                                                      "triplet_fp64"])
+def test_partial_rows_in_lds_and_in_the_workspace_agree(name, over):
+    import torch
+    from paper_1703_08977_amd import Ensemble
+    cfg = W.get(name, **over)
+    n = 100_000
+    a = Ensemble(cfg, n_walkers=n).init()
+    b = Ensemble(cfg, n_walkers=n).init()
+    ra = a.propagate(0, 300, 1).cpu().numpy()   # 301 rows: merged in the workspace
+    rb = b.propagate(0, 300, 2).cpu().numpy()   # 151 rows: merged in LDS
+    torch.cuda.synchronize()
+    assert np.array_equal(ra[::2], rb)
+    for t in ("x", "lnw", "el"):
+        assert torch.equal(getattr(a, t), getattr(b, t))
+    # the per-block rows the workspace keeps after the call agree as well
+    pa = a.block_rows(300, 1).cpu().numpy()
+    pb = b.block_rows(300, 2).cpu().numpy()
+    assert pa.shape[0] == pb.shape[0] and np.array_equal(pa[:, ::2], pb)

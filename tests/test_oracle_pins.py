@@ -773,3 +773,21 @@ def test_right_end_point_sum_of_the_exact_system():
     t = np.arange(11) * 20 * cfg["dt"]
     assert np.abs(est.log_mean_weight(r["samples"]) - 4.0 * t).max() < 1e-13
     assert np.abs(r["el"] + 4.0).max() < 1e-12
+
+
+def test_node_distance_diagnostic_is_the_minimum_along_the_path():
+    # the oracle's per-walker diagnostic: the smallest node-distance estimate 1/|grad ln|Phi|| over
+    # the positions the walker held while alive, rebuilt here by walking one step per call
+    cfg = W.get("he_2tripS_4m", precision="fp64", dt=0.01)
+    ids = np.arange(12) * 5 + 3
+    x0, _ = oracle.init(cfg, ids)
+    _, lnw_all, _, _, _, dmin = oracle.propagate(cfg, ids, x0, np.zeros(len(ids)), 0, 40, 40, node_dmin=True)
+    x, lnw = x0.copy(), np.zeros(len(ids))
+    best = np.array([1 / math.sqrt(oracle.trial_eval(cfg, x0[i]).gphi2) for i in range(len(ids))])
+    for k in range(40):
+        x, lnw, _, _, _ = oracle.propagate(cfg, ids, x, lnw, k, 1, 1)
+        for i in range(len(ids)):
+            if np.isfinite(lnw[i]):
+                best[i] = min(best[i], 1 / math.sqrt(oracle.trial_eval(cfg, x[i]).gphi2))
+    assert np.array_equal(np.isfinite(lnw), np.isfinite(lnw_all))
+    assert np.allclose(dmin, best, rtol=1e-12, atol=0)
