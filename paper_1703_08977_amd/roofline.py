@@ -45,14 +45,16 @@ F32 = {"sqrt": (0, 1), "rcp": (0, 1), "dist": (1, 1), "exp": (1, 1), "expm1": (1
 # binary64 (hefk_f64math.hpp, counted from the code, a binary64 select as two 32-bit selects):
 # sqrt  = seed, coupled iteration, correction (8); rcp = seed + two Newton steps (5);
 # dist  = seed, the coupled iteration of sqrt, one Newton step on 1/r (11);
-# exp   = reduction (4), 13 series terms, 2^k and the underflow guard (22);
-# expm1 = reduction (4), 11 series terms, e^r - 1 from r (2), 2^k, 2^k - 1, guard and fused sum (24);
+# exp   = reduction (4), the degree-11 polynomial (11), 2^k and the underflow guard (5): 20;
+# expm1 = reduction (4), the degree-10 polynomial Q (10), r + r^2 Q (2), 2^k, 2^k - 1, guard and
+#         fused sum (7): 23;
 # log   = exponent and mantissa fields (3), halving above sqrt 2 (5), s = (m - 1)/(m + 1) (8), z (1),
-#         10 series terms (9), 2 s (1 + z p) (3), the exponent's two-part ln 2 (3), times -2 dt (1): 34;
-# sincos = quadrant reduction (5), t^2 (1), sin series (9), cos series (8), the quadrant's
-#         exchange (5) and its sign bits (7): 35
-F64 = {"sqrt": (8, 0), "rcp": (5, 0), "dist": (11, 0), "exp": (22, 0), "expm1": (24, 0), "log": (34, 0),
-       "sincos": (35, 0)}
+#         the degree-6 polynomial R (6), 2 s (1 + z R) (3), the exponent's two-part ln 2 (3),
+#         times -2 dt (1): 31;
+# sincos = quadrant reduction (4), y^2 (1), sin(pi y) = y S(y^2) (7), cos(pi y) = C(y^2) (7), the
+#         quadrant's exchange (5) and its sign bits (7): 31
+F64 = {"sqrt": (8, 0), "rcp": (5, 0), "dist": (11, 0), "exp": (20, 0), "expm1": (23, 0), "log": (31, 0),
+       "sincos": (31, 0)}
 
 
 class _Count:

@@ -274,6 +274,9 @@ HOST_CASES = [
 
 @pytest.mark.parametrize("name,over", HOST_CASES, ids=lambda v: str(v))
 def test_kernel_arithmetic_host_build_matches_oracle(name, over):
+    # 1e-12 per walker; for a trial with a node, the one walker whose path came closest to the
+    # node may reach 1e-10: there one Euler step multiplies a rounding difference of the two
+    # sides' elementary functions by about dt/d^2 (d the node distance), as on the GPU
     cfg = W.get(name, **over)
     ids = np.arange(48) * 13 + 1
     h = host_run(cfg, ids, 300, 20)
@@ -282,9 +285,14 @@ def test_kernel_arithmetic_host_build_matches_oracle(name, over):
     assert np.array_equal(np.isfinite(h["lnw"]), np.isfinite(r["lnw"]))
     f = np.isfinite(r["ell"])
     assert np.array_equal(f, np.isfinite(h["ell"]))
-    assert np.abs(h["ell"][f] - r["ell"][f]).max() < 1e-12
     alive = np.isfinite(r["lnw"])
-    assert np.abs(h["x"][alive] - r["x"][alive]).max() < 1e-12
+    err = np.where(f, np.abs(np.where(f, h["ell"] - r["ell"], 0.0)), 0.0).max(axis=1)
+    err = np.maximum(err, np.where(alive, np.abs(h["x"] - r["x"]).max(axis=1), 0.0))
+    if cfg["trial"] in ("triplet", "pz", "triplet_r0", "pz_sum"):
+        closest = int(np.argmin(r["node_dmin"]))
+        assert err[closest] < 1e-10, err[closest]
+        err[closest] = 0.0
+    assert err.max() < 1e-12, (err.max(), ids[int(np.argmax(err))])
 
 
 # --------------------------------------------------------------------------
