@@ -287,7 +287,11 @@ size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_steps, int32_t 
  * tape with the noise regenerated from Philox, then one reverse-mode pass
  * through the trial evaluation per step gives grad_Y and d_theta of
  * dt lambda . b + A_j (E_L - e_ref) (lambda the adjoint of the position,
- * A_j the weight of step j's local energy in J).
+ * A_j the weight of step j's local energy in J).  With ckpt_every = 1 the
+ * checkpoints are the whole trajectory (56 bytes per walker-step: 14.7 GB for
+ * 2^18 walkers x 1000 steps) and the sweep reads the positions directly, with
+ * no recomputation and no tape in the scratch; the result is bitwise that of
+ * any other ckpt_every, as the recomputed positions are the stored ones.
  *   ckpt    : device, the checkpoints [n_steps/ckpt_every + 1][7][N] of that call;
  *   samples : device, its sample rows (m and S0 give each walker's share of L_s);
  *   gL      : HOST, [n_steps / sample_every + 1], or twice that with HE_FK_GRAD_MOMENT2;

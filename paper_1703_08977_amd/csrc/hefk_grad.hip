@@ -4,6 +4,9 @@
 // one thread per walker walks the checkpoint segments backwards, recomputes
 // each segment from its checkpoint into a scratch tape (noise regenerated
 // from Philox), and runs the adjoint recursion of hefk_adjoint.hpp over it.
+// With a checkpoint at every step the stored trajectory is read directly and
+// nothing is recomputed (binary64 trajectories of 2^18 walkers x 1000 steps
+// take 14.7 GB of device memory).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -23,9 +26,12 @@ namespace {
 
 constexpr int kGradBlock = 256;
 // Minimum resident waves per SIMD the gradient kernel is compiled for (register budget 512 / waves):
-// 3 keeps it free of spills (4 spills 164 B per lane and is no faster)
+// 3 keeps the recomputing sweep free of spills (4 spills 164 B per lane and is no faster)
 #ifndef HEFK_GRAD_WAVES
 #define HEFK_GRAD_WAVES 3
+#endif
+#ifndef HEFK_GRAD_DIRECT_WAVES
+#define HEFK_GRAD_DIRECT_WAVES 3
 #endif
 
 struct GArgs {
@@ -71,6 +77,14 @@ struct DeviceTape {
         for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
     }
     __device__ double get_lnw(int slot) const { return tape[(size_t)slot * 7 * n + 6 * n + i]; }
+    // the checkpoints as the stored trajectory (one per step)
+    __device__ void load_pos(int c, double y[6]) const
+    {
+        const double* b = ckpt + (size_t)c * 7 * n;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
+    }
+    __device__ double load_lnw(int c) const { return ckpt[(size_t)c * 7 * n + 6 * n + i]; }
 };
 
 struct SampleView {
@@ -84,8 +98,9 @@ struct SampleView {
     __device__ double g2s(int s) const { return g2 ? g2[s] : 0.0; }
 };
 
-template <int TRIAL, int NOISE>
-__global__ __launch_bounds__(kGradBlock, HEFK_GRAD_WAVES) void grad_kernel(const GArgs a)
+template <int TRIAL, int NOISE, bool DIRECT>
+__global__ __launch_bounds__(kGradBlock, DIRECT ? HEFK_GRAD_DIRECT_WAVES : HEFK_GRAD_WAVES) void grad_kernel(
+    const GArgs a)
 {
     __shared__ double red[8];
     const int64_t i = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;
@@ -100,8 +115,11 @@ __global__ __launch_bounds__(kGradBlock, HEFK_GRAD_WAVES) void grad_kernel(const
         DeviceTape tape{a.ckpt, a.tape, a.n, i};
         SampleView sv{a.samples, a.g, a.g2};
         double P = 0.0, Q = 0.0;
-        walker_reverse<TRIAL, NOISE>(a.tp, a.sc, a.ss, st, a.n_steps, a.sample_every, a.ckpt_every, sv,
-                                     tape, gth, &P, &Q);
+        if constexpr (DIRECT)
+            walker_reverse_direct<TRIAL>(a.tp, a.sc, a.ss, a.n_steps, a.sample_every, sv, tape, gth, &P, &Q);
+        else
+            walker_reverse<TRIAL, NOISE>(a.tp, a.sc, a.ss, st, a.n_steps, a.sample_every, a.ckpt_every, sv,
+                                         tape, gth, &P, &Q);
         if (a.score) {
             double y0[6], l0, sc[2];
             tape.load_ckpt(0, y0, l0);
@@ -155,16 +173,19 @@ __global__ __launch_bounds__(kGradBlock) void grad_sum_kernel(const double* __re
 
 typedef void (*GradFn)(GArgs);
 
-GradFn pick(int trial, int noise)
+// the direct sweep regenerates no noise: one kernel per trial serves every noise kind
+GradFn pick(int trial, int noise, bool direct)
 {
     if (trial == TRIAL_EXPO) {
-        if (noise == NOISE_G1) return grad_kernel<TRIAL_EXPO, NOISE_G1>;
-        if (noise == NOISE_G2) return grad_kernel<TRIAL_EXPO, NOISE_G2>;
-        return grad_kernel<TRIAL_EXPO, NOISE_PM1>;
+        if (direct) return grad_kernel<TRIAL_EXPO, NOISE_G1, true>;
+        if (noise == NOISE_G1) return grad_kernel<TRIAL_EXPO, NOISE_G1, false>;
+        if (noise == NOISE_G2) return grad_kernel<TRIAL_EXPO, NOISE_G2, false>;
+        return grad_kernel<TRIAL_EXPO, NOISE_PM1, false>;
     }
-    if (noise == NOISE_G1) return grad_kernel<TRIAL_PADE, NOISE_G1>;
-    if (noise == NOISE_G2) return grad_kernel<TRIAL_PADE, NOISE_G2>;
-    return grad_kernel<TRIAL_PADE, NOISE_PM1>;
+    if (direct) return grad_kernel<TRIAL_PADE, NOISE_G1, true>;
+    if (noise == NOISE_G1) return grad_kernel<TRIAL_PADE, NOISE_G1, false>;
+    if (noise == NOISE_G2) return grad_kernel<TRIAL_PADE, NOISE_G2, false>;
+    return grad_kernel<TRIAL_PADE, NOISE_PM1, false>;
 }
 
 struct Layout {
@@ -187,7 +208,8 @@ int layout(const he_fk_params* p, int64_t n_steps, int32_t sample_every, int32_t
     if (L->blocks > INT32_MAX) return HE_FK_EINVAL;
     auto up256 = [](size_t b) { return (b + 255) & ~size_t(255); };
     L->tape = 0;
-    L->partial = up256((size_t)(ckpt_every + 1) * 7 * (size_t)n * sizeof(double));
+    // the recomputing sweep's segment tape; the direct sweep (ckpt_every = 1) needs none
+    L->partial = ckpt_every == 1 ? 0 : up256((size_t)(ckpt_every + 1) * 7 * (size_t)n * sizeof(double));
     L->g = L->partial + up256((size_t)L->blocks * 2 * sizeof(double));
     L->total = L->g + up256((size_t)2 * (n_steps / sample_every + 1) * sizeof(double));
     return HE_FK_OK;
@@ -257,7 +279,7 @@ extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const doubl
     if (hipMemcpyAsync((void*)a.g, gL, (size_t)n_g * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return HE_FK_EDEVICE;
     const int nk = p->noise == HE_FK_NOISE_PM1 ? NOISE_PM1 : (p->contract == 2 ? NOISE_G2 : NOISE_G1);
-    hipLaunchKernelGGL(pick(p->trial, nk), dim3((unsigned)L.blocks), dim3(kGradBlock), 0, s, a);
+    hipLaunchKernelGGL(pick(p->trial, nk, ckpt_every == 1), dim3((unsigned)L.blocks), dim3(kGradBlock), 0, s, a);
     if (hipGetLastError() != hipSuccess) return HE_FK_EDEVICE;
     hipLaunchKernelGGL(grad_sum_kernel, dim3(1), dim3(kGradBlock), 0, s, (const double*)a.partial, (int)L.blocks,
                        dtheta);

@@ -283,18 +283,26 @@ def _vjp(c: _Count, f, trial: str):
 
 
 def grad_tape_bytes_per_walker_step(cfg: dict) -> float:
-    """Tape traffic of the reverse sweep per walker-step: the recomputed position (6 binary64
-    coordinates) written once and read back once, and ln w likewise at the sampling steps."""
-    return 2.0 * 6 * 8 + 2.0 * 8 / max(1, int(cfg.get("sample_every", 1)))
+    """HBM traffic of the reverse sweep per walker-step.  Recomputing segments: the recomputed
+    position (6 binary64 coordinates) written to the segment tape once and read back once, and
+    ln w likewise at the sampling steps.  Over the stored trajectory (a checkpoint at every
+    step): the position read once, and ln w at the sampling steps."""
+    se = max(1, int(cfg.get("sample_every", 1)))
+    if int(cfg.get("ckpt_every", 50)) == 1:
+        return 6 * 8 + 8.0 / se
+    return 2.0 * 6 * 8 + 2.0 * 8 / se
 
 
 def grad_slots_per_walker_step(cfg: dict) -> float:
-    """VALU issue slots of the gradient kernel per walker-step: the recomputed forward step
-    (plus the segment's start evaluation, once per checkpoint interval) and the reverse step."""
-    fwd = count(dict(cfg, precision="fp64"))
-    c = _Count()
-    _trial(c, F64, cfg["trial"])
+    """VALU issue slots of the gradient kernel per walker-step: the reverse step, and when the
+    sweep recomputes segments, the recomputed forward step (plus the segment's start
+    evaluation, once per checkpoint interval)."""
     v = _Count()
     _vjp(v, F64, cfg["trial"])
     ce = max(1, int(cfg.get("ckpt_every", 50)))
+    if ce == 1:
+        return float(v.main + v.trans)
+    fwd = count(dict(cfg, precision="fp64"))
+    c = _Count()
+    _trial(c, F64, cfg["trial"])
     return float(fwd.main + fwd.trans + (c.main + c.trans) / ce + v.main + v.trans)

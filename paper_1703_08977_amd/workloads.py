@@ -57,10 +57,11 @@ HE_TRIPLET_4M = dict(
     n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0)
 
 # Gradient of E(T = 2) with respect to (alpha, beta) of the Pade-Jastrow trial:
-# 2^18 walkers, dt = 0.002, 1000 steps, checkpoints every 50 steps.
+# 2^18 walkers, dt = 0.002, 1000 steps, a checkpoint at every step: the stored
+# trajectory (14.7 GB in binary64) is the reverse sweep's tape, and nothing is recomputed.
 HE_GRAD_PADE_256K = dict(
     name="he_1s_pade_grad_256k", trial="pade", theta=[2.0, 0.25, 0.5, 0.0], Z=2.0, ee=1,
-    n_walkers=1 << 18, dt=0.002, n_steps=1000, sample_every=50, ckpt_every=50, seed=0,
+    n_walkers=1 << 18, dt=0.002, n_steps=1000, sample_every=50, ckpt_every=1, seed=0,
     e_ref=-2.8754, noise="gauss", quad="trapezoid", contract=1, precision="fp64",
     n_metropolis=500, metropolis_sigma=0.5, init_sigma=1.0, gd_steps=20, gd_lr=0.05)
 

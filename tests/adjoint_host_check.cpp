@@ -1,5 +1,6 @@
 // Host build of the gradient's per-walker reverse sweep (hefk_sweep.hpp) for
-// CPU checks against the oracle's complex-step derivative.
+// CPU checks against the oracle's complex-step derivative.  ckpt_every = 1 runs
+// the sweep that reads the stored trajectory instead of recomputing segments.
 //
 // stdin line 1: trial ee quad contract n_met Z t0 t1 t2 t3 dt e_ref metropolis_sigma init_sigma seed
 //               n_steps sample_every ckpt_every
@@ -30,6 +31,12 @@ struct HostTape {
         for (int k = 0; k < 6; ++k) y[k] = tp[7 * s + k];
     }
     double get_lnw(int s) const { return tp[7 * s + 6]; }
+    // the checkpoints as the stored trajectory (ckpt_every = 1)
+    void load_pos(int c, double y[6]) const
+    {
+        for (int k = 0; k < 6; ++k) y[k] = ck[7 * c + k];
+    }
+    double load_lnw(int c) const { return ck[7 * c + 6]; }
 };
 
 struct HostSamples {
@@ -71,7 +78,10 @@ void one(const TrialParams<double>& tp, const StepConst& sc, int n_met, double m
         if ((k + 1) % ce == 0) save((k + 1) / ce);
     }
     double gth[2] = {0, 0}, P = 0, Q = 0;
-    walker_reverse<TRIAL, NOISE>(tp, sc, ss, st, n_steps, se, ce, hs, tape, gth, &P, &Q);
+    if (ce == 1)
+        walker_reverse_direct<TRIAL>(tp, sc, ss, n_steps, se, hs, tape, gth, &P, &Q);
+    else
+        walker_reverse<TRIAL, NOISE>(tp, sc, ss, st, n_steps, se, ce, hs, tape, gth, &P, &Q);
     std::printf("%.17g %.17g %.17g %.17g\n", gth[0], gth[1], P, Q);
 }
 

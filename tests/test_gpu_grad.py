@@ -44,7 +44,8 @@ def _grad(e, ckpt, s, cfg, gL, flags=0):
 
 
 @pytest.mark.parametrize("over,ce", [({}, 50), ({"quad": "right"}, 25), ({"contract": 2}, 100),
-                                     ({"noise": "pm1"}, 50), ({"trial": "expo", "theta": [1.8]}, 50)])
+                                     ({"noise": "pm1"}, 50), ({"trial": "expo", "theta": [1.8]}, 50), ({}, 1),
+                                     ({"quad": "right", "noise": "pm1"}, 1), ({"trial": "expo", "theta": [1.8]}, 1)])
 def test_grad_matches_oracle_complex_step(over, ce):
     cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, ckpt_every=ce, **over)
     n = 3001
@@ -54,6 +55,27 @@ def test_grad_matches_oracle_complex_step(over, ce):
     y0 = x0.t().contiguous().cpu().numpy()
     ref = oracle.grad_objective(cfg, np.arange(n), y0, 200, 50, gL)
     assert np.abs(got - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-3), (got, ref)
+
+
+@pytest.mark.parametrize("over", [{}, {"quad": "right"}])
+def test_sweep_over_the_stored_trajectory_equals_the_recomputing_sweep(over):
+    # a checkpoint at every step makes the reverse sweep read the stored positions instead
+    # of recomputing segments: the same bits, with the score and second-moment terms on
+    from paper_1703_08977_amd import _lib
+    n = 1 << 16
+    gL = np.zeros(21)
+    gL[-1], gL[-2], gL[7] = -10.0, 10.0, 0.5
+    gL2 = np.zeros(21)
+    gL2[-1], gL2[3] = 0.7, -0.2
+    flags = _lib.GRAD_SCORE | _lib.GRAD_MOMENT2
+    got = {}
+    for ce in (1, 50, 10):
+        cfg = W.get("he_1s_pade_grad_256k", n_walkers=n, ckpt_every=ce, **over)
+        e, ckpt, s, x0 = _forward(cfg)
+        got[ce] = _grad(e, ckpt, s, cfg, np.concatenate([gL, gL2]), flags=flags)
+        del e, ckpt
+    print("dtheta", got)
+    assert np.array_equal(got[1], got[50]) and np.array_equal(got[1], got[10]), got
 
 
 def test_grad_score_term_matches_oracle():
@@ -109,8 +131,9 @@ def test_weight_variance_gradient_through_autograd_against_central_differences()
 
 
 def test_grad_full_size_against_central_differences():
-    # 2^18 walkers x 1000 steps, checkpoints every 50: d E(T=2) / d(alpha, beta) against
-    # central differences of the GPU forward map at the same start positions and noise.
+    # 2^18 walkers x 1000 steps, a checkpoint at every step (the reverse sweep reads the
+    # stored trajectory): d E(T=2) / d(alpha, beta) against central differences of the
+    # GPU forward map at the same start positions and noise.
     cfg = W.get("he_1s_pade_grad_256k")
     e, ckpt, s, x0 = _forward(cfg)
     dts = cfg["dt"] * cfg["sample_every"]

@@ -300,8 +300,9 @@ def test_kernel_arithmetic_host_build_matches_oracle(name, over):
 # complex-step derivative (two independent methods for the same quantity).
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("over,ckpt_every", [({}, 50), ({}, 25), ({"quad": "right"}, 50),
-                                             ({"trial": "expo", "theta": [1.8]}, 50), ({"contract": 2}, 100)])
+@pytest.mark.parametrize("over,ckpt_every", [({}, 50), ({}, 25), ({}, 1), ({"quad": "right"}, 50),
+                                             ({"quad": "right"}, 1), ({"trial": "expo", "theta": [1.8]}, 50),
+                                             ({"contract": 2}, 100)])
 def test_reverse_sweep_host_build_matches_complex_step(over, ckpt_every):
     cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, **over)
     ids = np.arange(192) * 31 + 5
@@ -323,6 +324,20 @@ def test_reverse_sweep_host_build_matches_complex_step(over, ckpt_every):
         assert abs(got[d] - ref[d]) <= 1e-11 * max(abs(ref[d]), 1e-3)
     assert abs(a[:, 3].sum() - gL2.sum()) < 1e-12                 # the shares q_is sum to one per row
     assert abs(a[:, 2].sum() - gL.sum() - 2 * gL2.sum()) < 1e-12
+
+
+@pytest.mark.parametrize("over", [{}, {"quad": "right"}, {"trial": "expo", "theta": [1.8]}])
+def test_reverse_sweep_over_the_stored_trajectory_equals_the_recomputing_one(over):
+    # with a checkpoint at every step the sweep reads the positions instead of recomputing
+    # segments; the recomputed positions are the stored ones, so the two agree bitwise
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, **over)
+    ids = np.arange(64) * 97 + 3
+    r = oracle.run(cfg, ids, 200, 50)
+    gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
+    gL2 = np.array([0.0, 0.5, 0.0, -0.8, 1.2])
+    direct = adjoint_host_run(cfg, ids, 200, 50, 1, r["samples"], gL, gL2)
+    for ce in (50, 10):
+        assert np.array_equal(direct, adjoint_host_run(cfg, ids, 200, 50, ce, r["samples"], gL, gL2)), ce
 
 
 def test_binary64_step_functions_against_the_c_library():

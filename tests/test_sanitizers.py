@@ -80,11 +80,12 @@ def test_reverse_sweep_host_build_under_sanitizers():
     r = oracle.run(cfg, ids, 200, 50)
     gL = np.zeros(len(r["samples"]))
     gL[-1], gL[-2] = -10.0, 10.0
-    saved = T._ADJ
-    try:
-        T._ADJ = exe
-        s = T.adjoint_host_run(cfg, ids, 200, 50, 50, r["samples"], gL)
-    finally:
-        T._ADJ = saved
-    p = T.adjoint_host_run(cfg, ids, 200, 50, 50, r["samples"], gL)
-    assert np.array_equal(s, p)
+    for ce in (50, 1):  # the recomputing sweep and the one over the stored trajectory
+        saved = T._ADJ
+        try:
+            T._ADJ = exe
+            s = T.adjoint_host_run(cfg, ids, 200, 50, ce, r["samples"], gL)
+        finally:
+            T._ADJ = saved
+        p = T.adjoint_host_run(cfg, ids, 200, 50, ce, r["samples"], gL)
+        assert np.array_equal(s, p), ce
