@@ -77,12 +77,12 @@ struct DeviceTape {
         for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
     }
     __device__ double get_lnw(int slot) const { return tape[(size_t)slot * 7 * n + 6 * n + i]; }
-    // the checkpoints as the stored trajectory (one per step)
+    // the checkpoints as the stored trajectory (one per step), each read once: streaming loads
     __device__ void load_pos(int c, double y[6]) const
     {
         const double* b = ckpt + (size_t)c * 7 * n;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
+        for (int k = 0; k < 6; ++k) y[k] = __builtin_nontemporal_load(b + (int64_t)k * n + i);
     }
     __device__ double load_lnw(int c) const { return ckpt[(size_t)c * 7 * n + 6 * n + i]; }
 };

@@ -204,9 +204,11 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
                 until_ckpt = a.ckpt_every;
                 if (valid) {
                     double* cp = a.ckpt + (size_t)crow * 7 * (size_t)n;
+                    // streaming stores: a checkpoint is written once and read once, by the
+                    // gradient's reverse sweep, long after (a trajectory when ckpt_every = 1)
 #pragma unroll
-                    for (int kk = 0; kk < 6; ++kk) cp[(int64_t)kk * n + i] = (double)w.y[kk];
-                    cp[6 * n + i] = w.lnw;
+                    for (int kk = 0; kk < 6; ++kk) __builtin_nontemporal_store((double)w.y[kk], cp + (int64_t)kk * n + i);
+                    __builtin_nontemporal_store(w.lnw, cp + 6 * n + i);
                 }
                 ++crow;
             }
