@@ -15,6 +15,7 @@
 
 #include "he_fk.h"
 #include "hefk_adjoint.hpp"
+#include "hefk_layout.hpp"
 #include "hefk_reduce.hpp"
 #include "hefk_sweep.hpp"
 
@@ -24,7 +25,7 @@ int check_params(const he_fk_params* p);  // hefk_kernels.hip
 
 namespace {
 
-constexpr int kGradBlock = 256;
+constexpr int kGradBlock = layout::kLanes;
 // Minimum resident waves per SIMD the gradient kernel is compiled for (register budget 512 / waves):
 // 3 keeps the recomputing sweep free of spills (4 spills 164 B per lane and is no faster)
 #ifndef HEFK_GRAD_WAVES
@@ -58,33 +59,33 @@ struct DeviceTape {
     int64_t n, i;
     __device__ void load_ckpt(int c, double y[6], double& lnw) const
     {
-        const double* b = ckpt + (size_t)c * 7 * n;
+        const double* b = ckpt + layout::ckpt_row(c, n);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
-        lnw = b[6 * n + i];
+        for (int k = 0; k < 6; ++k) y[k] = b[layout::coord(k, n, i)];
+        lnw = b[layout::coord(6, n, i)];
     }
     __device__ void put(int slot, const double y[6])
     {
-        double* b = tape + (size_t)slot * 7 * n;
+        double* b = tape + layout::ckpt_row(slot, n);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) b[(int64_t)k * n + i] = y[k];
+        for (int k = 0; k < 6; ++k) b[layout::coord(k, n, i)] = y[k];
     }
-    __device__ void put_lnw(int slot, double lnw) { tape[(size_t)slot * 7 * n + 6 * n + i] = lnw; }
+    __device__ void put_lnw(int slot, double lnw) { tape[layout::ckpt_row(slot, n) + layout::coord(6, n, i)] = lnw; }
     __device__ void get(int slot, double y[6]) const
     {
-        const double* b = tape + (size_t)slot * 7 * n;
+        const double* b = tape + layout::ckpt_row(slot, n);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = b[(int64_t)k * n + i];
+        for (int k = 0; k < 6; ++k) y[k] = b[layout::coord(k, n, i)];
     }
-    __device__ double get_lnw(int slot) const { return tape[(size_t)slot * 7 * n + 6 * n + i]; }
+    __device__ double get_lnw(int slot) const { return tape[layout::ckpt_row(slot, n) + layout::coord(6, n, i)]; }
     // the checkpoints as the stored trajectory (one per step), each read once: streaming loads
     __device__ void load_pos(int c, double y[6]) const
     {
-        const double* b = ckpt + (size_t)c * 7 * n;
+        const double* b = ckpt + layout::ckpt_row(c, n);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = __builtin_nontemporal_load(b + (int64_t)k * n + i);
+        for (int k = 0; k < 6; ++k) y[k] = __builtin_nontemporal_load(b + layout::coord(k, n, i));
     }
-    __device__ double load_lnw(int c) const { return ckpt[(size_t)c * 7 * n + 6 * n + i]; }
+    __device__ double load_lnw(int c) const { return ckpt[layout::ckpt_row(c, n) + layout::coord(6, n, i)]; }
 };
 
 struct SampleView {
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kGradBlock, DIRECT ? HEFK_GRAD_DIRECT_WAVES : HEFK_
     const GArgs a)
 {
     __shared__ double red[8];
-    const int64_t i = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;
+    const int64_t i = layout::walker((int64_t)blockIdx.x, threadIdx.x);
     double gth[2] = {0.0, 0.0};
     if (i < a.n) {
         const uint64_t gid = a.walker_offset + (uint64_t)i;
@@ -193,7 +194,7 @@ struct Layout {
     int64_t blocks;
 };
 
-int layout(const he_fk_params* p, int64_t n_steps, int32_t sample_every, int32_t ckpt_every, Layout* L)
+int grad_layout(const he_fk_params* p, int64_t n_steps, int32_t sample_every, int32_t ckpt_every, Layout* L)
 {
     int rc = check_params(p);
     if (rc) return rc;
@@ -224,7 +225,7 @@ extern "C" size_t he_fk_grad_scratch_bytes(const he_fk_params* p, int64_t n_step
                                            int32_t ckpt_every)
 {
     Layout L;
-    if (layout(p, n_steps, sample_every, ckpt_every, &L)) return 0;
+    if (grad_layout(p, n_steps, sample_every, ckpt_every, &L)) return 0;
     return L.total;
 }
 
@@ -233,7 +234,7 @@ extern "C" int he_fk_grad(const he_fk_params* p, const double* ckpt, const doubl
                           size_t scratch_bytes, double* dtheta, void* stream)
 {
     Layout L;
-    int rc = layout(p, n_steps, sample_every, ckpt_every, &L);
+    int rc = grad_layout(p, n_steps, sample_every, ckpt_every, &L);
     if (rc) return rc;
     if (!ckpt || !samples || !gL || !scratch || !dtheta) return HE_FK_EINVAL;
     if (flags & ~(HE_FK_GRAD_SCORE | HE_FK_GRAD_MOMENT2)) return HE_FK_EINVAL;

@@ -10,11 +10,12 @@
 
 #include "he_fk.h"
 #include "hefk_device.hpp"
+#include "hefk_layout.hpp"
 #include "hefk_reduce.hpp"
 
 namespace hefk {
 
-constexpr int kBlock = 256;  // 4 waves of 64 lanes; one walker per lane
+constexpr int kBlock = layout::kLanes;  // 4 waves of 64 lanes; one walker per lane
 
 // Minimum resident waves per SIMD the propagate kernels are compiled for
 // (register budget 512 / waves: 80 registers in binary32, 128 in binary64).  At these
@@ -109,7 +110,7 @@ __device__ __forceinline__ Stream make_stream(const KArgs& a, int64_t i)
 template <typename R, int TRIAL>
 __global__ __launch_bounds__(kBlock) void init_kernel(const KArgs a)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = layout::walker((int64_t)blockIdx.x, threadIdx.x);
     if (i >= a.n) return;
     const Stream st = make_stream(a, i);
     double y[6];
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const KArgs a)
     trial_eval<R, TRIAL>(tparams<R>(a), yr, b, el);
     R* x = (R*)a.x;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) x[(int64_t)k * a.n + i] = yr[k];
+    for (int k = 0; k < 6; ++k) x[layout::coord(k, a.n, i)] = yr[k];
     ((R*)a.el)[i] = el;
     a.lnw[i] = 0.0;
 }
@@ -146,11 +147,11 @@ __device__ __forceinline__ void sample_row(const KArgs& a, int row, double* rows
     if (threadIdx.x == 0) {
         // two paths, so that each row access has a known address space (LDS or global)
         if (a.rows_in_lds) {
-            double* r = rows_lds + (size_t)row * 8;
+            double* r = rows_lds + layout::row_offset(row);
             if (!first) t = merge_tuple(load_tuple(r), t);
             store_tuple(r, t);
         } else {
-            double* r = rows_out + (size_t)row * 8;
+            double* r = rows_out + layout::row_offset(row);
             if (!first) t = merge_tuple(load_tuple(r), t);
             store_tuple(r, t);
         }
@@ -166,27 +167,27 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
     const TrialParams<R>& tp = tparams<R>(a);
     const StepScale<R>& ss = sscale<R>(a);
     const int64_t n = a.n;
-    const int64_t n_chunks = (n + kBlock - 1) / kBlock;
-    double* const rows_out = a.partials + (size_t)blockIdx.x * (size_t)a.n_samples * 8;
+    const int64_t n_chunks = layout::chunks(n);
+    double* const rows_out = a.partials + HEFK_BLOCK_ROWS(blockIdx.x, a.n_samples);
     R* x = (R*)a.x;
 
     for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const bool first = (c == (int64_t)blockIdx.x);
-        const int64_t i = c * kBlock + threadIdx.x;
+        const int64_t i = layout::walker(c, threadIdx.x);
         const bool valid = i < n;
         const int64_t ii = valid ? i : n - 1;  // tail lanes shadow the last walker, never stored or counted
         const Stream st = make_stream(a, ii);
         WalkerState<R> w;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) w.y[k] = x[(int64_t)k * n + ii];
+        for (int k = 0; k < 6; ++k) w.y[k] = x[layout::coord(k, n, ii)];
         w.lnw = a.lnw[ii];
         walker_reset<R, TRIAL, EXT>(tp, a.sc, ss, w);
 
         sample_row<R>(a, 0, rows_out, rows_lds, first, valid, w, red);
         if (a.ckpt && valid) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) a.ckpt[(int64_t)k * n + i] = (double)w.y[k];
-            a.ckpt[6 * n + i] = w.lnw;
+            for (int k = 0; k < 6; ++k) a.ckpt[layout::coord(k, n, i)] = (double)w.y[k];
+            a.ckpt[layout::coord(6, n, i)] = w.lnw;
         }
 
         int row = 1, until_sample = a.sample_every, until_ckpt = a.ckpt_every, crow = 1;
@@ -203,19 +204,20 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
             if (a.ckpt && --until_ckpt == 0) {
                 until_ckpt = a.ckpt_every;
                 if (valid) {
-                    double* cp = a.ckpt + (size_t)crow * 7 * (size_t)n;
+                    double* cp = a.ckpt + layout::ckpt_row(crow, n);
                     // streaming stores: a checkpoint is written once and read once, by the
                     // gradient's reverse sweep, long after (a trajectory when ckpt_every = 1)
 #pragma unroll
-                    for (int kk = 0; kk < 6; ++kk) __builtin_nontemporal_store((double)w.y[kk], cp + (int64_t)kk * n + i);
-                    __builtin_nontemporal_store(w.lnw, cp + 6 * n + i);
+                    for (int kk = 0; kk < 6; ++kk)
+                        __builtin_nontemporal_store((double)w.y[kk], cp + layout::coord(kk, n, i));
+                    __builtin_nontemporal_store(w.lnw, cp + layout::coord(6, n, i));
                 }
                 ++crow;
             }
         }
         if (valid) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) x[(int64_t)k * n + i] = w.y[k];
+            for (int k = 0; k < 6; ++k) x[layout::coord(k, n, i)] = w.y[k];
             a.lnw[i] = w.lnw;
             ((R*)a.el)[i] = w.el;
         }
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(const double* __restrict_
     const int s = blockIdx.x;
     Tuple t = empty_tuple();
     for (int b = threadIdx.x; b < n_parts; b += kBlock)
-        t = merge_tuple(t, load_tuple(partials + ((size_t)b * n_samples + s) * 8));
+        t = merge_tuple(t, load_tuple(partials + layout::block_rows(b, n_samples) + layout::row_offset(s)));
     store_tuple(sh + threadIdx.x * 8, t);
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -375,7 +377,7 @@ static KArgs make_args(const he_fk_params* p)
 // Dynamic LDS of a propagate launch: the block's partial rows when they fit.
 static size_t rows_lds_bytes(int64_t n_samples)
 {
-    const size_t b = (size_t)n_samples * 8 * sizeof(double);
+    const size_t b = layout::row_offset(n_samples) * sizeof(double);
     return b <= (size_t)kRowsLdsBytes ? b : 0;
 }
 
@@ -390,13 +392,7 @@ static int propagate_grid(const he_fk_params* p, size_t lds_bytes, int64_t* out)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, lds_bytes) != hipSuccess)
         return HE_FK_EDEVICE;
     if (per_cu < 1) per_cu = 1;
-    const int64_t n_chunks = (p->n_walkers + kBlock - 1) / kBlock;
-    int64_t g = (int64_t)cus * per_cu;
-    if (g > n_chunks) g = n_chunks;
-    // same number of chunks per block for as many blocks as possible
-    const int64_t per_block = (n_chunks + g - 1) / g;
-    g = (n_chunks + per_block - 1) / per_block;
-    *out = g;
+    *out = layout::grid(layout::chunks(p->n_walkers), (int64_t)cus * per_cu);
     return HE_FK_OK;
 }
 
@@ -427,7 +423,7 @@ static int propagate_launch(const he_fk_params* p, const he_fk_walkers* w, int64
     int64_t g = 0;
     rc = propagate_grid(p, lds, &g);
     if (rc) return rc;
-    const size_t need = (size_t)g * (size_t)n_samples * 8 * sizeof(double);
+    const size_t need = layout::block_rows(g, n_samples) * sizeof(double);
     if (workspace_bytes < need) return HE_FK_ESCRATCH;
     KArgs a = make_args(p);
     a.x = w->x;
@@ -493,7 +489,7 @@ int he_fk_init(const he_fk_params* p, const he_fk_walkers* w, void* stream)
     a.lnw = w->lnw;
     a.el = w->el;
     KernelFn fn = p->precision == HE_FK_MIXED ? pick_init_r<float>(p->trial) : pick_init_r<double>(p->trial);
-    const int64_t blocks = (p->n_walkers + kBlock - 1) / kBlock;
+    const int64_t blocks = layout::chunks(p->n_walkers);
     if (blocks > INT32_MAX) return HE_FK_EINVAL;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? HE_FK_OK : HE_FK_EDEVICE;
@@ -505,7 +501,7 @@ size_t he_fk_propagate_workspace_bytes(const he_fk_params* p, int64_t n_steps, i
     const int64_t n_samples = n_steps / sample_every + 1;
     int64_t g = 0;
     if (propagate_grid(p, rows_lds_bytes(n_samples), &g)) return 0;
-    return (size_t)g * (size_t)n_samples * 8 * sizeof(double);
+    return layout::block_rows(g, n_samples) * sizeof(double);
 }
 
 int he_fk_propagate(const he_fk_params* p, const he_fk_walkers* w, int64_t step0, int64_t n_steps,

@@ -4,7 +4,9 @@ AddressSanitizer and UndefinedBehaviorSanitizer into a driver that runs the
 noise, quadrature and variant, and the complex-step gradient; and the host
 builds of the kernels' per-walker code (step and reverse sweep) with the same
 sanitizers on their host side, run over trial, noise and variant cases in both
-precisions.  Any report ends the program with a nonzero status."""
+precisions; and a replay of the kernels' loop nests whose every array index goes
+through the kernels' own layout functions, checked against the host allocation
+sizes.  Any report ends the program with a nonzero status."""
 import os
 import shutil
 import subprocess
@@ -89,3 +91,50 @@ def test_reverse_sweep_host_build_under_sanitizers():
             T._ADJ = saved
         p = T.adjoint_host_run(cfg, ids, 200, 50, ce, r["samples"], gL)
         assert np.array_equal(s, p), ce
+
+
+def _layout_cases():
+    """Configurations of the host replay of the kernels' loop nests: walker counts with
+    ragged tails, resident block counts from 1 to more than the chunks, sampling and
+    checkpoint spacings, partial rows in LDS (when they fit, as the launcher decides) or in
+    the workspace; and the full sizes of the mixed P_z bench step (2^24 walkers, 1536
+    resident blocks: the grid of 1525 the profiles show) and of the gradient workload's
+    trajectory at a reduced walker count."""
+    cases = []
+    for n in (1, 255, 256, 257, 3001, 65541):
+        for res in (1, 7, 1536, 6100):
+            for steps, se, ce in ((300, 100, 0), (200, 50, 1), (200, 50, 25), (300, 1, 0), (1000, 50, 50)):
+                ns = steps // se + 1
+                cases.append((n, res, steps, se, ce, int(ns * 64 <= 16384)))
+    cases.append((1 << 24, 1536, 12000, 100, 0, 1))
+    cases.append((4099, 3072, 1000, 50, 1, 1))
+    return cases
+
+
+@pytest.fixture(scope="module")
+def layout_check():
+    exe = os.path.join(tempfile.mkdtemp(prefix="hefk_layout_"), "layout_host_check")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-I", T.CSRC, "-o", exe, os.path.join(T.ROOT, "tests", "layout_host_check.cpp")])
+    return exe
+
+
+def test_kernel_index_arithmetic_replayed_under_sanitizers(layout_check):
+    # every index of init, propagate, merge and the gradient sweeps through the kernels' own
+    # layout functions, checked against the host allocation sizes; each walker's state and
+    # each checkpoint entry written exactly once, each chunk visited once
+    cases = _layout_cases()
+    stdin = "".join("%d %d %d %d %d %d\n" % c for c in cases)
+    r = subprocess.run([layout_check], input=stdin, capture_output=True, text=True, env=ENV)
+    out = r.stdout.split("\n")
+    assert r.returncode == 0 and "runtime error" not in r.stderr and "ERROR" not in r.stderr, (r.stdout[-2000:],
+                                                                                                r.stderr[-2000:])
+    assert sum(1 for line in out if line.startswith("ok")) == len(cases)
+    assert out[len(cases) - 2] == "ok grid=1525"
+
+
+def test_kernel_index_replay_catches_a_short_array(layout_check):
+    # the same replay with the checkpoint array one element short must report the access
+    r = subprocess.run([layout_check], input="257 7 200 50 25 1\n", capture_output=True, text=True,
+                       env=dict(ENV, HEFK_LAYOUT_SHORT="1"))
+    assert r.returncode == 1 and "outside" in r.stdout and "ckpt" in r.stdout, r.stdout
