@@ -78,6 +78,26 @@ def test_sweep_over_the_stored_trajectory_equals_the_recomputing_sweep(over):
     assert np.array_equal(got[1], got[50]) and np.array_equal(got[1], got[10]), got
 
 
+@pytest.mark.parametrize("ce", [1, 50])
+def test_grad_matches_the_host_build_of_the_same_sweep(ce):
+    # the GPU adjoint against the same reverse sweep compiled for the host (one walker at a
+    # time, its own start ensemble and noise), on the GPU's sample rows: per walker the same
+    # arithmetic, so the sums over walkers agree to 1e-12
+    import math
+    from hefk_testutil import adjoint_host_run
+    from paper_1703_08977_amd import _lib
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, ckpt_every=ce)
+    n = 2048
+    e, ckpt, s, x0 = _forward(cfg, n)
+    gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
+    gL2 = np.array([0.0, 0.5, 0.0, -0.8, 1.2])
+    got = _grad(e, ckpt, s, cfg, np.concatenate([gL, gL2]), flags=_lib.GRAD_MOMENT2)
+    host = adjoint_host_run(cfg, np.arange(n), 200, 50, ce, s.cpu().numpy(), gL, gL2)
+    ref = np.array([math.fsum(host[:, d]) for d in range(2)])
+    print("gpu", got, "host", ref, "diff", got - ref)
+    assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-3), (got, ref)
+
+
 def test_grad_score_term_matches_oracle():
     cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, ckpt_every=50)
     n = 2048
