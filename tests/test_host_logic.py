@@ -340,6 +340,27 @@ def test_reverse_sweep_over_the_stored_trajectory_equals_the_recomputing_one(ove
         assert np.array_equal(direct, adjoint_host_run(cfg, ids, 200, 50, ce, r["samples"], gL, gL2)), ce
 
 
+@pytest.mark.parametrize("over", [{}, {"quad": "right"}, {"trial": "expo", "theta": [1.8]}])
+@pytest.mark.parametrize("ckpt_every", [1, 50])
+def test_reverse_sweep_per_walker_against_the_tangent(over, ckpt_every):
+    # the dot-product test, walker by walker: each walker's adjoint gradient (host build of the
+    # reverse sweep) against its tangent, sum_s (g_s p_is + 2 g2_s q_is) d l_is / d theta with
+    # the oracle's complex-step d l_is / d theta, to 1e-13 of the largest walker term
+    cfg = W.get("he_1s_pade_grad_256k", n_steps=200, sample_every=50, **over)
+    ids = np.arange(96) * 37 + 11
+    r = oracle.run(cfg, ids, 200, 50)
+    gL = np.array([0.0, 0.3, -0.7, 1.1, -0.5])
+    gL2 = np.array([0.0, 0.5, 0.0, -0.8, 1.2])
+    m, s0, s2 = r["samples"][:, 0], r["samples"][:, 1], r["samples"][:, 3]
+    p = np.exp(r["ell"] - m) / s0
+    q = np.exp(2.0 * (r["ell"] - m)) / s2
+    host = adjoint_host_run(cfg, ids, 200, 50, ckpt_every, r["samples"], gL, gL2)
+    for d in range(2):
+        dl = oracle.dlnw_dtheta(cfg, ids, r["x0"], 200, 50, d)
+        ref = (gL * p * dl).sum(axis=1) + (gL2 * 2.0 * q * dl).sum(axis=1)
+        assert np.abs(host[:, d] - ref).max() <= 1e-13 * np.abs(ref).max(), d
+
+
 def test_binary64_step_functions_against_the_c_library():
     # host build of the binary64 elementary functions of the step (series and Newton
     # forms written for its argument ranges): errors in units of the last place over
