@@ -36,7 +36,9 @@ def parse():
                     help="timed FP64 steps on the first seeds of the mixed leg, for the speedup and the paired "
                          "mixed - FP64 energy difference (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=16384)
+    ap.add_argument("--cpu-walkers", type=int, default=0,
+                    help="walkers of the oracle's timed sample (0: 131072 of the bench workload, about 13 s on 16 "
+                         "host threads; grad mode: the whole 2^18-walker gradient workload, about 11 s)")
     ap.add_argument("--grad-walkers", type=int, default=0,
                     help="grad mode: walkers of the gradient workload (0: its own 2^18)")
     ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
@@ -283,6 +285,7 @@ def grad_bench(n_timed, n_warmup, cpu_walkers, no_cpu, n_walkers=0):
            "dE_dtheta": grads, "roofline": roof}
     if not no_cpu:
         import oracle
+        cpu_walkers = cpu_walkers or n
         ids = np.arange(cpu_walkers)
         t0 = time.perf_counter()
         y0, _ = oracle.init(cfg, ids)
@@ -469,7 +472,7 @@ def main():
                                           "runs share their increments and start ensemble"}
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_walkers)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_walkers or 131072)
         print("# cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     torch.cuda.synchronize()
