@@ -139,11 +139,11 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const KArgs a)
 #define HEFK_ROWS_LDS_BYTES 16384  // 256 sample rows of 64 bytes per block (0: rows merged in the workspace)
 #endif
 constexpr int kRowsLdsBytes = HEFK_ROWS_LDS_BYTES;
-template <typename R>
+template <typename R, bool OWN_EXP>
 __device__ __forceinline__ void sample_row(const KArgs& a, int row, double* rows_out, double* rows_lds, bool first,
                                            bool valid, const WalkerState<R>& w, double* red)
 {
-    Tuple t = block_tuple(valid, w.lnw, (double)w.el, red);
+    Tuple t = block_tuple<OWN_EXP>(valid, w.lnw, (double)w.el, red);
     if (threadIdx.x == 0) {
         // two paths, so that each row access has a known address space (LDS or global)
         if (a.rows_in_lds) {
@@ -162,6 +162,11 @@ template <typename R, int TRIAL, int NOISE, bool EXT>
 __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void propagate_kernel(
     const KArgs a)
 {
+    // the binary64 variant kernels (plain walk, node bridge) of the two-orbital trials take
+    // the sample weights by the step's own exp: the library's spilled part of their step
+    // loop to scratch (measured: P_z with the bridge 3.5 % and fn 7 with bridge and plain walk
+    // 9 % faster without it; the other kernels measured the same or faster as they are)
+    constexpr bool kOwnExp = sizeof(R) == 8 && EXT && TRIAL != TRIAL_EXPO && TRIAL != TRIAL_PADE;
     __shared__ double red[kRedSlots];
     extern __shared__ double rows_lds[];  // [n_samples][8] when a.rows_in_lds
     const TrialParams<R>& tp = tparams<R>(a);
@@ -183,7 +188,7 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
         w.lnw = a.lnw[ii];
         walker_reset<R, TRIAL, EXT>(tp, a.sc, ss, w);
 
-        sample_row<R>(a, 0, rows_out, rows_lds, first, valid, w, red);
+        sample_row<R, kOwnExp>(a, 0, rows_out, rows_lds, first, valid, w, red);
         if (a.ckpt && valid) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) a.ckpt[layout::coord(k, n, i)] = (double)w.y[k];
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(kBlock, (propagate_waves<R, TRIAL, EXT>())) void pr
             walker_step<R, TRIAL, EXT>(tp, a.sc, ss, inc, w);
             if (--until_sample == 0) {
                 until_sample = a.sample_every;
-                sample_row<R>(a, row, rows_out, rows_lds, first, valid, w, red);
+                sample_row<R, kOwnExp>(a, row, rows_out, rows_lds, first, valid, w, red);
                 ++row;
             }
             if (a.ckpt && --until_ckpt == 0) {

@@ -15,6 +15,8 @@
 
 #include <cmath>
 
+#include "hefk_f64math.hpp"
+
 namespace hefk {
 
 struct Tuple {
@@ -135,6 +137,10 @@ constexpr int kRedSlots = 4 * 8;  // 4 waves x 8 doubles
 // call's second barrier, and thread 0 has read its sums red[4..] before it
 // reaches the next call's first barrier, which the next sums are written after;
 // so consecutive calls need no barrier between them.
+// OWN_EXP: the weights e^(ln w - m) by the step's own binary64 exp (hefk_f64math.hpp), in
+// the binary64 kernels: the library exp needs more registers than their step loop leaves
+// free and spilled part of the loop's state to scratch.
+template <bool OWN_EXP = false>
 __device__ __forceinline__ Tuple block_tuple(bool valid, double lnw, double el, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -145,7 +151,7 @@ __device__ __forceinline__ Tuple block_tuple(bool valid, double lnw, double el, 
     if (lane == 0) red[wave] = mw;
     __syncthreads();
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const double e = alive ? exp(lnw - m) : 0.0;
+    const double e = alive ? (OWN_EXP ? f64::exp(lnw - m) : exp(lnw - m)) : 0.0;
     const double s0 = wave_sum(e);
     const double s1 = wave_sum(alive ? e * el : 0.0);
     const double s2 = wave_sum(e * e);
