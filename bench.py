@@ -43,8 +43,9 @@ def parse():
                     help="grad mode: walkers of the gradient workload (0: its own 2^18)")
     ap.add_argument("--oracle-threads", type=int, default=0, help="oracle mode: thread count (0: all)")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy", "oracle", "grad", "cases"],
-                    help="copy: a plain 1 GiB device copy, three times (the reference reading of the HBM "
-                         "byte counters FETCH_SIZE / WRITE_SIZE); oracle: time the CPU oracle alone on the "
+                    help="copy: a plain 1 GiB device copy, three times after a warm-up (the reference reading of the HBM "
+                         "byte counters FETCH_SIZE / WRITE_SIZE), then three sums over 8 GiB (a read-only "
+                         "stream), with the rates both reach; oracle: time the CPU oracle alone on the "
                          "4096-walker ground state in full and on walkers 0..65535 of the Pade ground state "
                          "at dt = 0.002; grad: the pathwise gradient of E(T = 2) for the Pade-Jastrow trial, "
                          "2^18 walkers x 1000 steps (forward storing the trajectory, then he_fk_grad reading it back), with the "
@@ -55,14 +56,37 @@ def parse():
 
 
 def copy_reference():
+    """Three plain 1 GiB device copies (the reading of the byte counters), then three sums over
+    8 GiB (a read-only stream): the HBM rates these plain kernels reach, timed with events after
+    one untimed call of each."""
     import torch
     nbytes = 1 << 30
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
+    dst.copy_(src)  # warm-up
+    copy_rate = []
     for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"mode": "copy", "bytes_per_copy": nbytes, "copies": 3}), flush=True)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_rate.append(2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e12)
+    del src, dst
+    rbytes = 8 << 30
+    big = torch.ones(rbytes // 8, dtype=torch.float64, device="cuda")
+    total = big.sum()  # warm-up
+    read_rate = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        total = big.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        read_rate.append(rbytes / (e0.elapsed_time(e1) * 1e-3) / 1e12)
+    assert float(total) == rbytes // 8
+    print(json.dumps({"mode": "copy", "bytes_per_copy": nbytes, "copies": 3, "copy_TB_per_s": copy_rate,
+                      "read_bytes": rbytes, "read_TB_per_s": read_rate}), flush=True)
 
 
 def run_leg(cfg, n_steps_timed, n_warmup, seeds):
