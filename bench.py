@@ -406,7 +406,7 @@ def main():
         return
     import torch
     from paper_1703_08977_amd import workloads as W
-    from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, fp32_flops_per_walker_step,
+    from paper_1703_08977_amd.roofline import (PEAK_SLOTS_PER_S, class_counts, fp32_flops_per_walker_step,
                                                instructions_per_walker_step, slots_per_walker_step,
                                                transcendentals_per_walker_step)
 
@@ -430,18 +430,20 @@ def main():
     achieved = slots * n * K / kern / 1e12
     peak = PEAK_SLOTS_PER_S / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-            "frac_is": "VALU main-pipe issue utilisation: formula-counted main-pipe slots per second over "
-                       "256 CU x 4 SIMD x 16 lanes x 2.4 GHz (the 78.6 TFLOP/s FMA rate / 2); the hardware "
-                       "transcendentals issue beside the main pipe and are counted apart",
+            "frac_is": "VALU issue utilisation: the step's formula-counted instructions, each class at its "
+                       "issue cost measured on this GPU (slots of 2 SIMD-cycles per wave64 instruction: "
+                       "binary32 and 32-bit integer 1, binary64 2.1, binary32 transcendental 4.1, ...), per "
+                       "second, over 256 CU x 4 SIMD x 32 lanes x 2.4 GHz (the 157.3 TFLOP/s binary32 "
+                       "rate in fused multiply-adds)",
             "traffic": committed_traffic(cfg), "kernel": "propagate_kernel", "slots_per_walker_step": slots,
+            "instructions_by_class": class_counts(cfg),
             "transcendentals_per_walker_step": transcendentals_per_walker_step(cfg),
             "valu_instructions_per_walker_step": instructions_per_walker_step(cfg), "kernel_ms": kern * 1e3}
     fl = fp32_flops_per_walker_step(cfg)
     if fl:
         roof["fp32_flops_per_walker_step"] = fl
         roof["fp32_tflops"] = fl * n * K / kern / 1e12
-        roof["fp32_flop_frac_of_78.6_unpacked"] = roof["fp32_tflops"] / 78.6
-        roof["fp32_flop_frac_of_157.3_packed"] = roof["fp32_tflops"] / 157.3
+        roof["fp32_flop_frac_of_157.3"] = roof["fp32_tflops"] / 157.3
 
     out = {
         "metric": "He walker-steps/s/GPU; mixed FP32 vs FP64 time-to-1e-5 Ha energy error",
@@ -466,9 +468,11 @@ def main():
         leg = run_leg(c64, n64, 0, seeds[:n64])
         w64 = sum(leg["walls"]) / len(leg["walls"])
         k64 = sum(leg["kern"]) / len(leg["kern"])
+        s64 = slots_per_walker_step(c64)
         out["fp64"] = {"value": n * K / w64, "ms_per_step": w64 * 1e3, "propagate_walker_steps_per_s": n * K / k64,
                        "E_window": leg["energies"], "jackknife_se": leg["errs"],
-                       "slots_per_walker_step": slots_per_walker_step(c64)}
+                       "slots_per_walker_step": s64, "instructions_by_class": class_counts(c64),
+                       "roofline_frac": s64 * n * K / k64 / PEAK_SLOTS_PER_S}
         out["speedup_mixed_vs_fp64"] = w64 / wall
         # paired mixed - FP64 difference on identical seeds, and the time to a 1e-5 Ha standard error
         m = len(leg["energies"])

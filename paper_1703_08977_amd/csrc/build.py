@@ -50,7 +50,23 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    if not os.environ.get("HEFK_LIBRARY"):
+        build_rates(verbose)
     return LIB
+
+
+RATES = os.path.join(PKG, "valu_rates")
+
+
+def build_rates(verbose: bool = False) -> str:
+    """The issue-cost calibration program (valu_rates.hip): a standalone executable."""
+    tmp = RATES + ".tmp"
+    cmd = [hipcc()] + flags() + [os.path.join(HERE, "valu_rates.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, RATES)
+    return RATES
 
 
 if __name__ == "__main__":

@@ -4,28 +4,47 @@ The step is per-walker scalar arithmetic (transcendental, integer and
 floating point; no contraction, no HBM traffic between sampling times), so
 its roofline is the vector-ALU issue rate.
 
-Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-operations/s,
-one main-pipe VALU instruction slot per lane per clock (a wave64 instruction
-occupies a 16-lane SIMD for 4 clocks).  This is the published 78.6 TFLOP/s
-binary32 (and binary64) FMA rate divided by 2 flops; the 157.3 TFLOP/s
-binary32 figure needs packed (v_pk_*) instructions, which this library does
-not use.
+Peak: the published binary32 vector rate, 157.3 TFLOP/s = 256 CUs x 4 SIMDs x
+32 lanes x 2.4 GHz fused multiply-adds: 78.64e12 issue slots per second, one
+slot being one lane of one binary32 add, multiply or fused multiply-add.  On
+this GPU that rate needs no packed instructions: a wave64 binary32 or 32-bit
+integer instruction with vector operands issues every 2.1-2.2 SIMD-cycles
+(`valu_rates`, profiles/valu_class_costs.txt), and this library uses no
+packed (v_pk_*) arithmetic.
 
-Work: every elementary operation of the step's formulas counts one main-pipe
-slot -- add, mul, fma, compare, select, convert, 32-bit integer op,
-32x32->64 multiply, three-input xor.  The binary32 hardware transcendentals
-(v_sqrt, v_rsq, v_rcp, v_exp, v_log, v_sin, v_cos) are counted apart: they
-issue beside the main pipe.  The counters show it: the mixed P_z step's 205
-VALU instructions per wave-step (20 of them transcendental) issue at 0.262
-wave-instructions per SIMD-cycle at 2.38 GHz, above the 0.25 that one 4-cycle
-slot per instruction would allow, so the roofline is the main pipe's.
-Binary64 functions count their polynomial and range-reduction operations (the
-table F64 below), a binary64 select as two 32-bit selects.  Counts follow the
-formulas term by term (they are not read back from the compiled code).
+Work: the step's formulas, counted term by term (not read back from the
+compiled code), in classes of instruction; each class costs its issue time
+measured by `valu_rates` on the MI355X (SIMD-cycles per wave64 instruction,
+the lower of the class alone and beside binary32 multiply-adds), in slots of
+2 SIMD-cycles:
+
+  a32    binary32 add, mul, fma, compare, min/max; 32-bit integer add, logic,
+         shift, bit-field ops (three-input xor included)      2.0   -> 1
+  sel    32-bit select (a binary64 select is two)              2.31  -> 1.16
+  cvt    32-bit integer -> binary32 conversion                 2.48  -> 1.24
+  cvt64  conversion to or from binary64                        3.55  -> 1.77
+  mad    32 x 32 -> 64-bit integer multiply (Philox)           4.27  -> 2.14
+  f64    binary64 add, mul, fma, compare, ldexp, rounding      4.18  -> 2.09
+  trans  binary32 hardware transcendental (sqrt, rsq, rcp,
+         exp2, log2, sin, cos)                                 8.23  -> 4.12
+  seed   binary64 reciprocal or reciprocal square root seed   16.09  -> 8.04
+
+(The a32 cost is the published rate's 2 cycles; binary32 add and multiply
+measured 2.14-2.17, the 32-bit xor 2.24, the multiply-add 2.15-2.8 by operand
+layout.  Select, conversion and 32x32->64 multiply cost 4.1, 5.4 and 5.8
+cycles alone and the lower figures above beside multiply-adds.)  A
+transcendental does not issue beside the multiply-adds: with one beside each
+multiply-add the pair costs the sum of the two.
 """
 from __future__ import annotations
 
-PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 39.32e12
+from collections import Counter
+
+PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9  # 78.64e12: the 157.3 TFLOP/s binary32 rate in fused multiply-adds
+
+# slots (2 SIMD-cycles) per wave64 instruction of each class, from the measured issue costs above
+CLASS_SLOTS = {"a32": 1.0, "sel": 1.16, "cvt": 1.24, "cvt64": 1.77, "mad": 2.14, "f64": 2.09, "trans": 4.12,
+               "seed": 8.04}
 
 NODE_TRIALS = ("triplet", "triplet_r0", "pz", "pz_sum")
 
@@ -34,46 +53,71 @@ NODE_TRIALS = ("triplet", "triplet_r0", "pz", "pz_sum")
 # block index (the step, a scalar) and the walker id (fixed), so it needs only the xor
 # that joins them; round 2's product of the fixed word is fixed too.  The key schedule
 # runs on the scalar unit.
-PHILOX_BLOCK = 10 * (2 + 2) - 3 - 1
+PHILOX_BLOCK = {"mad": 10 * 2 - 2 - 1, "a32": 10 * 2 - 1}  # 17 + 19
 
-# (elementary operations, hardware transcendental instructions) per function
-# "dist": r and 1/r from a squared distance q -- binary32 one reciprocal square root and the
-# product q (1/r); binary64 a square root and a reciprocal.  "expm1" (arguments <= 0):
-# binary32 the series to x^7 beside e^x - 1 and a select, binary64 the reduced series.
-F32 = {"sqrt": (0, 1), "rcp": (0, 1), "dist": (1, 1), "exp": (1, 1), "expm1": (11, 1), "log": (1, 1),
-       "sincos": (0, 2)}
+# instruction classes per function
+# binary32: "dist" (r and 1/r from a squared distance q) is one reciprocal square root and the
+# product q (1/r); "expm1" (arguments <= 0) the series to x^7 beside e^x - 1 and a select.
+F32 = {"sqrt": {"trans": 1}, "rcp": {"trans": 1}, "dist": {"a32": 1, "trans": 1}, "exp": {"a32": 1, "trans": 1},
+       "expm1": {"a32": 10, "sel": 1, "trans": 1}, "log": {"a32": 1, "trans": 1}, "sincos": {"trans": 2}}
 # binary64 (hefk_f64math.hpp, counted from the code, a binary64 select as two 32-bit selects):
-# sqrt  = seed, coupled iteration, correction (8); rcp = seed + two Newton steps (5);
-# dist  = seed, the coupled iteration of sqrt, one Newton step on 1/r (11);
-# exp   = reduction (4), the degree-11 polynomial (11), 2^k and the underflow guard (5): 20;
-# expm1 = reduction (4), the degree-10 polynomial Q (10), r + r^2 Q (2), 2^k, 2^k - 1, guard and
-#         fused sum (7): 23;
-# log   = exponent and mantissa fields (3), halving above sqrt 2 (5), s = (m - 1)/(m + 1) (8), z (1),
-#         the degree-6 polynomial R (6), 2 s (1 + z R) (3), the exponent's two-part ln 2 (3),
-#         times -2 dt (1): 31;
+# sqrt  = seed, coupled iteration and correction (7);
+# rcp   = seed, two Newton steps (4);
+# dist  = seed, the coupled iteration of sqrt, one Newton step on 1/r (10);
+# exp   = reduction (4), the degree-11 polynomial (11), 2^k (a conversion and ldexp) and the
+#         underflow guard (a compare, a select: 2 + 2);
+# expm1 = reduction (4), the degree-10 polynomial Q (10), r + r^2 Q (2), 2^k (conversion, ldexp),
+#         2^k - 1, the guard (compare, select) and the fused sum;
+# log   = exponent and mantissa fields (3 integer), halving above sqrt 2 (compare, product, the
+#         mantissa's select, the exponent's increment: 5), s = (m - 1)/(m + 1) (two sums, a
+#         reciprocal, a product: 8), z (1), the degree-6 polynomial R (6), 2 s (1 + z R) (3), the
+#         exponent's conversion and two-part ln 2 (3), times -2 dt (1);
 # sincos = quadrant reduction (4), y^2 (1), sin(pi y) = y S(y^2) (7), cos(pi y) = C(y^2) (7), the
-#         quadrant's exchange (5) and its sign bits (7): 31
-F64 = {"sqrt": (8, 0), "rcp": (5, 0), "dist": (11, 0), "exp": (20, 0), "expm1": (23, 0), "log": (31, 0),
-       "sincos": (31, 0)}
+#         quadrant index and the exchange of sine and cosine (conversion, two selects: 5) and the
+#         sign bits (7)
+F64 = {"sqrt": {"seed": 1, "f64": 7}, "rcp": {"seed": 1, "f64": 4}, "dist": {"seed": 1, "f64": 10},
+       "exp": {"f64": 4 + 11 + 1 + 1, "cvt64": 1, "sel": 2},
+       "expm1": {"f64": 4 + 10 + 2 + 1 + 1 + 1 + 1, "cvt64": 1, "sel": 2},
+       "log": {"a32": 3 + 1, "f64": 2 + 2 + 4 + 1 + 1 + 6 + 3 + 2 + 1, "sel": 2, "seed": 1, "cvt64": 1},
+       "sincos": {"f64": 4 + 1 + 7 + 7, "cvt64": 1, "sel": 4, "a32": 7}}
 
 
 class _Count:
-    def __init__(self):
-        self.main = 0.0
-        self.trans = 0.0
+    """Instruction counts of one walker step by class; `arith` is the class of the step's own
+    floating-point arithmetic (a32 in binary32, f64 in binary64)."""
 
-    def ops(self, n):
-        self.main += n
+    def __init__(self, arith: str = "a32"):
+        self.n = Counter()
+        self.arith = arith
+
+    def add(self, cls: str, k: float):
+        self.n[cls] += k
+
+    def ops(self, k: float):
+        self.n[self.arith] += k
 
     def fn(self, table, name, times=1):
-        m, t = table[name]
-        self.main += m * times
-        self.trans += t * times
+        for cls, k in table[name].items():
+            self.n[cls] += k * times
+
+    def philox(self, blocks: float):
+        for cls, k in PHILOX_BLOCK.items():
+            self.n[cls] += k * blocks
+
+    @property
+    def instructions(self) -> float:
+        return float(sum(self.n.values()))
+
+    @property
+    def slots(self) -> float:
+        return float(sum(k * CLASS_SLOTS[c] for c, k in self.n.items()))
 
 
 def _noise(c: _Count, f, noise: str, contract: int):
     if noise == "pm1":
-        c.ops(PHILOX_BLOCK / 20.0 + 6 * 2)  # one block per 20 steps; bit extract + select per coordinate
+        c.philox(1 / 20.0)  # one block per 20 steps
+        c.add("a32", 6)     # the bit of each coordinate
+        c.add("sel", 6)     # +-1 by a select
         return
     # Box-Muller per pair: the radius sqrt(dt) sqrt(-2 ln u1) as the square root of a scaled
     # logarithm, sin and cos of 2 pi u2; the radius-times-cosine products are the
@@ -82,12 +126,23 @@ def _noise(c: _Count, f, noise: str, contract: int):
         c.fn(f, "log")
         c.fn(f, "sqrt")
         c.fn(f, "sincos")
+    # each of the six uniforms: convert its integer field, then scale (binary32: one fused
+    # multiply-add with the half-unit offset; binary64: a product)
+    cvt = "cvt" if f is F32 else "cvt64"
     if contract == 2:
         # one block; the six 21-bit fields: four masks, and a shift, a shift and a
-        # shift-and-or for each of the two joined fields; convert + scale each
-        c.ops(PHILOX_BLOCK + 4 + 2 * 3 + 6 * 2)
+        # shift-and-or for each of the two joined fields
+        c.philox(1)
+        c.add("a32", 4 + 2 * 3)
+        c.add(cvt, 6)
+        c.ops(6)
+    elif f is F32:
+        c.philox(2)        # two blocks; each 23-bit field to [1, 2) by a funnel shift, then the offset
+        c.add("a32", 12)
     else:
-        c.ops(2 * PHILOX_BLOCK + 6 * 2)  # two blocks; funnel shift + add (binary32), convert + scale (binary64)
+        c.philox(2)
+        c.add(cvt, 6)
+        c.ops(6)
 
 
 def _trial(c: _Count, f, trial: str):
@@ -102,8 +157,9 @@ def _trial(c: _Count, f, trial: str):
         return
     # Jastrow: s = 1 + beta r12 and its reciprocal, 1/s^2, u', and the radial part of the local
     # energy's Jastrow terms [2 c beta (1/s + 2 + beta r12) - c^2 / s^2] / s^2 (5) plus the cusp
-    # remainder (ee - 2c)/r12 (product, select, sum: 3)
-    c.ops(1 + 1 + 1 + 5 + 3)
+    # remainder (ee - 2c)/r12 (product, select, sum: 3; a binary64 select is two)
+    c.ops(1 + 1 + 1 + 5 + 2)
+    c.add("sel", 1 if f is F32 else 2)
     c.fn(f, "rcp")
     if trial == "pade":
         # a_i (2), w = u'/r12 (1), drift, cosine difference (3),
@@ -111,8 +167,9 @@ def _trial(c: _Count, f, trial: str):
         c.ops(2 + 1 + drift + 3 + 5)
         return
     # d = (A - a)(r1 - r2) (2), its sign (1), the pair (t1, t2) (2 selects); the argument -|d| is
-    # an operand modifier in binary32 and a select in binary64, where a select takes two slots
-    c.ops(2 + 1 + 2 if f is F32 else 2 + 1 + 4 + 2)
+    # an operand modifier in binary32 and a select in binary64, where a select is two
+    c.ops(2 + 1)
+    c.add("sel", 2 if f is F32 else 4 + 2)
     if trial == "triplet":
         c.fn(f, "expm1")
         c.fn(f, "rcp")
@@ -145,40 +202,53 @@ def _trial(c: _Count, f, trial: str):
 def count(cfg: dict) -> _Count:
     prec = cfg.get("precision", "fp64")
     f = F32 if prec == "mixed" else F64
-    c = _Count()
+    c = _Count("a32" if f is F32 else "f64")
     _noise(c, f, cfg.get("noise", "gauss"), int(cfg.get("contract", 1)))
     _trial(c, f, cfg["trial"])
     c.ops(12)  # Euler step: Y + (dt f) b, then + r u, one fused multiply-add each per coordinate
     if cfg.get("drift_limit", 0.0) > 0:
         # |b|^2, 2 a dt |b|^2, 1 + ., 1 + sqrt, 2 / ., the drift's step factor dt f (the
-        # limited drift f b enters the next Euler step as (dt f) b), scale e (conversion + product)
-        c.ops(6 + 1 + 1 + 1 + 1 + 1 + 2)
+        # limited drift f b enters the next Euler step as (dt f) b), scale e (conversion to
+        # binary64 + binary64 product)
+        c.ops(6 + 1 + 1 + 1 + 1 + 1)
+        c.add("cvt64" if f is F32 else "f64", 1)
+        c.add("f64", 1)
         c.fn(f, "sqrt")
         c.fn(f, "rcp")
-    c.ops(1)  # the absorbed-walker test
+    c.add("f64", 1)  # the absorbed-walker test (ln w, binary64)
     if cfg["trial"] in NODE_TRIALS:
         # product of the orbital factor with the old sign and its test, the new sign
-        # (copysign), ln w = -inf on a crossing (two 32-bit selects)
-        c.ops(2 + 1 + 2)
-    c.ops(5)  # ln w update in binary64: conversion, shift by e_ref, quadrature (2), NaN guard
+        # (copysign, a 32-bit bit-field insert), ln w = -inf on a crossing (two 32-bit selects)
+        c.ops(2)
+        c.add("a32", 1)
+        c.add("sel", 2)
+    # ln w update in binary64: conversion of the local energy (a binary64 step's is a binary64
+    # operation), shift by e_ref, quadrature (2), NaN guard (select)
+    c.add("cvt64" if f is F32 else "f64", 1)
+    c.add("f64", 3)
+    c.add("sel", 1)
     return c
 
 
 def slots_per_walker_step(cfg: dict) -> float:
-    """Main-pipe VALU issue slots of one walker step (the elementary operations; the hardware
-    transcendentals issue beside them and are counted by transcendentals_per_walker_step)."""
-    return float(count(cfg).main)
+    """Issue slots of one walker step: every class's instructions at its measured cost
+    (CLASS_SLOTS), against PEAK_SLOTS_PER_S."""
+    return count(cfg).slots
 
 
 def instructions_per_walker_step(cfg: dict) -> float:
-    """VALU instructions of one walker step, transcendentals included (what SQ_INSTS_VALU counts)."""
-    c = count(cfg)
-    return float(c.main + c.trans)
+    """VALU instructions of one walker step (what SQ_INSTS_VALU counts per lane)."""
+    return count(cfg).instructions
 
 
 def transcendentals_per_walker_step(cfg: dict) -> float:
     """binary32 hardware transcendental instructions of one walker step (included in the slots)."""
-    return float(count(cfg).trans)
+    return float(count(cfg).n["trans"])
+
+
+def class_counts(cfg: dict) -> dict:
+    """Instructions of one walker step by class."""
+    return {k: float(v) for k, v in sorted(count(cfg).n.items())}
 
 
 # binary32 floating-point operations of the step, term by term from the formulas the step
@@ -297,12 +367,20 @@ def grad_slots_per_walker_step(cfg: dict) -> float:
     """VALU issue slots of the gradient kernel per walker-step: the reverse step, and when the
     sweep recomputes segments, the recomputed forward step (plus the segment's start
     evaluation, once per checkpoint interval)."""
-    v = _Count()
+    v = _Count("f64")
     _vjp(v, F64, cfg["trial"])
     ce = max(1, int(cfg.get("ckpt_every", 50)))
     if ce == 1:
-        return float(v.main + v.trans)
+        return v.slots
     fwd = count(dict(cfg, precision="fp64"))
-    c = _Count()
+    c = _Count("f64")
     _trial(c, F64, cfg["trial"])
-    return float(fwd.main + fwd.trans + (c.main + c.trans) / ce + v.main + v.trans)
+    return fwd.slots + c.slots / ce + v.slots
+
+
+def grad_instructions_per_walker_step(cfg: dict) -> float:
+    """VALU instructions of the reverse step per walker-step (the sweep over the stored
+    trajectory)."""
+    v = _Count("f64")
+    _vjp(v, F64, cfg["trial"])
+    return v.instructions
