@@ -20,18 +20,18 @@ the lower of the class alone and beside binary32 multiply-adds), in slots of
 
   a32    binary32 add, mul, fma, compare, min/max; 32-bit integer add, logic,
          shift, bit-field ops (three-input xor included)      2.0   -> 1
-  sel    32-bit select (a binary64 select is two)              2.31  -> 1.16
-  cvt    32-bit integer -> binary32 conversion                 2.48  -> 1.24
+  sel    32-bit select (a binary64 select is two)              2.28  -> 1.14
+  cvt    32-bit integer -> binary32 conversion                 2.46  -> 1.23
   cvt64  conversion to or from binary64                        3.55  -> 1.77
-  mad    32 x 32 -> 64-bit integer multiply (Philox)           4.27  -> 2.14
-  f64    binary64 add, mul, fma, compare, ldexp, rounding      4.18  -> 2.09
+  mad    32 x 32 -> 64-bit integer multiply (Philox)           4.12  -> 2.06
+  f64    binary64 add, mul, fma, compare, ldexp, rounding      4.17  -> 2.08
   trans  binary32 hardware transcendental (sqrt, rsq, rcp,
-         exp2, log2, sin, cos)                                 8.23  -> 4.12
-  seed   binary64 reciprocal or reciprocal square root seed   16.09  -> 8.04
+         exp2, log2, sin, cos)                                 8.24  -> 4.12
+  seed   binary64 reciprocal or reciprocal square root seed   16.07  -> 8.04
 
 (The a32 cost is the published rate's 2 cycles; binary32 add and multiply
-measured 2.14-2.17, the 32-bit xor 2.24, the multiply-add 2.15-2.8 by operand
-layout.  Select, conversion and 32x32->64 multiply cost 4.1, 5.4 and 5.8
+measured 2.15-2.17, the 32-bit xor 2.26, the multiply-add 2.16-2.8 by operand
+layout.  Select, conversion and 32x32->64 multiply cost 4.1, 5.5 and 5.8
 cycles alone and the lower figures above beside multiply-adds.)  A
 transcendental does not issue beside the multiply-adds: with one beside each
 multiply-add the pair costs the sum of the two.
@@ -43,7 +43,7 @@ from collections import Counter
 PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9  # 78.64e12: the 157.3 TFLOP/s binary32 rate in fused multiply-adds
 
 # slots (2 SIMD-cycles) per wave64 instruction of each class, from the measured issue costs above
-CLASS_SLOTS = {"a32": 1.0, "sel": 1.16, "cvt": 1.24, "cvt64": 1.77, "mad": 2.14, "f64": 2.09, "trans": 4.12,
+CLASS_SLOTS = {"a32": 1.0, "sel": 1.14, "cvt": 1.23, "cvt64": 1.77, "mad": 2.06, "f64": 2.08, "trans": 4.12,
                "seed": 8.04}
 
 NODE_TRIALS = ("triplet", "triplet_r0", "pz", "pz_sum")
