@@ -50,7 +50,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    if not os.environ.get("HEFK_LIBRARY"):  # a side build of the library (HEFK_LIBRARY) leaves it alone
+    if not os.environ.get("HEFK_LIBRARY"):
         build_rates(verbose)
     return LIB
 
