@@ -479,3 +479,20 @@ def test_fp32_flop_count_of_the_step_matches_the_counted_host_build(name, over):
     flops, trans = int(out[0]), int(out[1])
     assert roofline.fp32_flops_per_walker_step(cfg) == flops
     assert roofline.transcendentals_per_walker_step(cfg) == trans
+
+
+def test_roofline_class_costs_are_the_committed_calibration():
+    # every class cost the roofline charges is the one the committed calibration summary
+    # derives from its counters (the lower of the class alone and beside binary32 FMAs)
+    from paper_1703_08977_amd import roofline
+    with open(os.path.join(ROOT, "profiles", "valu_class_costs.txt")) as f:
+        text = f.read()
+    seen = set()
+    for m in re.finditer(r"^(\w+)\s+beside FMAs\s+([\d.]+)\s+alone\s+([\d.]+)\s+->\s+([\d.]+) cycles = ([\d.]+) slots",
+                         text, re.M):
+        cls, mix, alone, use, slots = m.group(1), *map(float, m.groups()[1:])
+        assert abs(use - min(mix, alone)) < 0.006 and abs(slots - use / 2) < 0.006, m.group(0)
+        assert abs(roofline.CLASS_SLOTS[cls] - slots) < 0.006, (cls, roofline.CLASS_SLOTS[cls], slots)
+        seen.add(cls)
+    assert seen == set(roofline.CLASS_SLOTS) - {"a32"}, seen
+    assert roofline.CLASS_SLOTS["a32"] == 1.0  # the published rate: 2 SIMD-cycles per wave64 instruction
